@@ -1,0 +1,137 @@
+/*
+ * mialign -- pairwise sequence alignment on AMD Instinct MI355X (gfx950).
+ *
+ * C ABI of the library.  Every entry point computes the dynamic-programming
+ * recurrence of AnySeq Sec. III-A:
+ *
+ *   H(i,j) = max{ H(i-1,j-1) + sigma(q_i,s_j), E(i,j), F(i,j), nu }     Eq. (1)
+ *   E(i,j) = max{ E(i-1,j) + ge, H(i-1,j) + go + ge }                    Eq. (4)
+ *   F(i,j) = max{ F(i,j-1) + ge, H(i,j-1) + go + ge }                    Eq. (5)
+ *
+ * for query Q = q_1..q_n (rows i) and subject S = s_1..s_m (columns j).
+ * Scores are signed and added: a gap of length k scores go + k*ge, with
+ * go <= 0 and ge < 0 (the paper writes subtracted positive penalties; its
+ * experiments use this signed form, Sec. V).  go == 0 is the linear gap model
+ * of Eqs. (2)-(3).  The three modes follow the initialisation and optimum
+ * rules of Sec. III-A:
+ *   ALN_GLOBAL     H(i,0) = go + i*ge, H(0,j) = go + j*ge, nu = -inf, optimum H(n,m);
+ *   ALN_LOCAL      H(i,0) = H(0,j) = 0, nu = 0, optimum anywhere;
+ *   ALN_SEMIGLOBAL H(i,0) = H(0,j) = 0, nu = -inf, optimum in row n or column m.
+ *
+ * Conventions where the paper leaves a choice open (all results are unique):
+ *   - optimum ties: smallest i, then smallest j; local with best score 0 is
+ *     the empty alignment at (0,0);
+ *   - traceback priority in the no-gap state: diagonal, then the vertical gap
+ *     E (CIGAR I, consumes the query), then the horizontal gap F (CIGAR D),
+ *     the order of the relaxation function in Sec. III-B; inside a gap the
+ *     gap-open predecessor wins ties; local alignments start at the first
+ *     cell with H = 0, semi-global ones on row 0 or column 0.
+ *
+ * Memory and execution model:
+ *   - Pointers documented as DEVICE point to memory the caller allocated on
+ *     the current HIP device; HOST pointers are ordinary host memory.
+ *   - The library never allocates device memory in aln_align_batch,
+ *     aln_align_long or aln_traceback: the caller passes a workspace whose
+ *     size it obtains from the matching *_workspace_size call.  All calls are
+ *     asynchronous on `stream` and capturable in a HIP graph.
+ *   - Host-detectable errors return a negative aln_status_t and enqueue no
+ *     device work.  Problems found on the device are reported per pair in
+ *     aln_result_t.flags.
+ */
+#ifndef MIALIGN_H
+#define MIALIGN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t aln_status_t;
+#define ALN_OK 0
+#define ALN_E_INVALID (-1)     /* a null pointer, negative size or inconsistent argument */
+#define ALN_E_ALPHABET (-2)    /* alphabet_size outside 2..32 */
+#define ALN_E_SCORING (-3)     /* gap_open > 0, gap_extend >= 0, or scores too large to be exact */
+#define ALN_E_WORKSPACE (-4)   /* workspace smaller than the size query returned */
+#define ALN_E_DEVICE (-5)      /* a HIP call failed (launch or device query) */
+#define ALN_E_UNSUPPORTED (-6) /* a combination this build does not provide */
+
+#define ALN_GLOBAL 0
+#define ALN_LOCAL 1
+#define ALN_SEMIGLOBAL 2
+
+/* Scoring scheme (Sec. III-C composes a substitution function with a gap scheme). */
+typedef struct {
+  int32_t mode;          /* ALN_GLOBAL / ALN_LOCAL / ALN_SEMIGLOBAL */
+  int32_t alphabet_size; /* 2..32; sequence codes must lie in 0..alphabet_size-1 */
+  const int8_t* subst;   /* HOST, alphabet_size^2 row-major sigma(q,s); NULL => match/mismatch */
+  int32_t match;         /* sigma(a,a) when subst == NULL */
+  int32_t mismatch;      /* sigma(a,b), a != b, when subst == NULL */
+  int32_t gap_open;      /* go <= 0; 0 selects the linear model */
+  int32_t gap_extend;    /* ge < 0; a gap of length k scores go + k*ge */
+} aln_scoring_t;
+
+/* One result per pair, 32 bytes, written by the device. */
+typedef struct {
+  int32_t score;
+  int32_t q_begin, q_end; /* aligned query part is q[q_begin:q_end] (0-based, half-open);
+                             q_end is the DP row of the optimum; q_begin = -1 when score-only */
+  int32_t s_begin, s_end; /* same for the subject */
+  int32_t cigar_len;      /* CIGAR words written, or required when ALN_RES_CIGAR_TRUNC; 0 if score-only */
+  uint32_t flags;         /* ALN_RES_* */
+  int32_t reserved;
+} aln_result_t;
+
+/* call flags */
+#define ALN_SCORE_ONLY 0u
+#define ALN_TRACEBACK 1u   /* aln_align_batch: also write the canonical CIGAR of every pair */
+#define ALN_FORCE_INT32 2u /* skip the packed 16-bit path */
+#define ALN_FORCE_INT16 4u /* test hook: run local pairs in 16 bits even when the a-priori bound fails */
+
+/* result flags */
+#define ALN_RES_INT32_REDO 1u  /* the 16-bit pass saturated; the pair was recomputed in 32 bits */
+#define ALN_RES_CIGAR_TRUNC 2u /* CIGAR capacity too small; cigar_len holds the required count */
+#define ALN_RES_BAD_CODE 4u    /* a sequence code >= alphabet_size; no score computed */
+#define ALN_RES_TOO_LONG 8u    /* n > max_n or m > max_m (the bounds the workspace was sized for) */
+
+/* CIGAR words: (run_length << 4) | op, op 0 = M (match or mismatch), 1 = I (query letter
+ * against a gap), 2 = D (subject letter against a gap), in alignment order. */
+#define ALN_CIGAR_M 0u
+#define ALN_CIGAR_I 1u
+#define ALN_CIGAR_D 2u
+
+/* Bytes of device workspace aln_align_batch needs for n_pairs pairs whose lengths are at most
+ * max_n (queries) and max_m (subjects), for the given flags.  Returns ALN_OK and sets *bytes. */
+aln_status_t aln_batch_workspace_size(const aln_scoring_t* scoring, int64_t n_pairs, int64_t max_n,
+                                      int64_t max_m, uint32_t flags, size_t* bytes);
+
+/* Aligns n_pairs independent pairs (inter-sequence parallelism, Sec. VI; the batched form of the
+ * recurrence above).
+ *   q, s          DEVICE  concatenated uint8 codes of all queries / subjects
+ *   q_off, s_off  DEVICE  int64[n_pairs+1]; pair k is q[q_off[k]:q_off[k+1]] vs s[s_off[k]:s_off[k+1]]
+ *   max_n, max_m  upper bounds of the lengths (pairs above them get ALN_RES_TOO_LONG)
+ *   flags         ALN_SCORE_ONLY or ALN_TRACEBACK, optionally | ALN_FORCE_INT32 / ALN_FORCE_INT16
+ *   out           DEVICE  aln_result_t[n_pairs]
+ *   cigar         DEVICE  uint32 CIGAR words; pair k owns cigar[cigar_off[k]:cigar_off[k+1]]
+ *                         (n + m words always suffice); both NULL unless ALN_TRACEBACK
+ *   cigar_off     DEVICE  int64[n_pairs+1]
+ *   workspace     DEVICE  at least aln_batch_workspace_size(...) bytes, 256-byte aligned
+ * Ownership: the caller owns every buffer; nothing is retained after the call's work completes. */
+aln_status_t aln_align_batch(const aln_scoring_t* scoring, int64_t n_pairs, const uint8_t* q, const int64_t* q_off,
+                             const uint8_t* s, const int64_t* s_off, int64_t max_n, int64_t max_m, uint32_t flags,
+                             aln_result_t* out, uint32_t* cigar, const int64_t* cigar_off, void* workspace,
+                             size_t workspace_bytes, hipStream_t stream);
+
+/* Human-readable text of a status code (static storage). */
+const char* aln_status_string(aln_status_t status);
+
+/* Library version string. */
+const char* aln_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,202 @@
+"""mialign: pairwise sequence alignment on AMD MI355X (gfx950).
+
+Thin Python binding over the C ABI declared in ``include/mialign.h``.  It only
+marshals arguments: every step of the alignment runs in the HIP kernels of
+``libmialign.so``.  PyTorch supplies device memory and the HIP stream.  There
+is no CPU fallback: if the library is missing, importing the binding's entry
+points raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmialign.so")
+
+GLOBAL, LOCAL, SEMIGLOBAL = 0, 1, 2
+SCORE_ONLY, TRACEBACK, FORCE_INT32, FORCE_INT16 = 0, 1, 2, 4
+RES_INT32_REDO, RES_CIGAR_TRUNC, RES_BAD_CODE, RES_TOO_LONG = 1, 2, 4, 8
+CIGAR_M, CIGAR_I, CIGAR_D = 0, 1, 2
+
+STATUS = {0: "ALN_OK", -1: "ALN_E_INVALID", -2: "ALN_E_ALPHABET", -3: "ALN_E_SCORING", -4: "ALN_E_WORKSPACE",
+          -5: "ALN_E_DEVICE", -6: "ALN_E_UNSUPPORTED"}
+
+RESULT_DTYPE = np.dtype([("score", "<i4"), ("q_begin", "<i4"), ("q_end", "<i4"), ("s_begin", "<i4"),
+                         ("s_end", "<i4"), ("cigar_len", "<i4"), ("flags", "<u4"), ("reserved", "<i4")])
+
+
+class AlnError(RuntimeError):
+    def __init__(self, status: int, what: str = ""):
+        self.status = status
+        super().__init__("%s%s (%d)" % (what + ": " if what else "", STATUS.get(status, "?"), status))
+
+
+class aln_scoring_t(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int32), ("alphabet_size", ctypes.c_int32), ("subst", ctypes.POINTER(ctypes.c_int8)),
+                ("match", ctypes.c_int32), ("mismatch", ctypes.c_int32), ("gap_open", ctypes.c_int32),
+                ("gap_extend", ctypes.c_int32)]
+
+
+_lib = None
+
+_SIGNATURES = {
+    "aln_batch_workspace_size": (ctypes.c_int32, [ctypes.POINTER(aln_scoring_t), ctypes.c_int64, ctypes.c_int64,
+                                                  ctypes.c_int64, ctypes.c_uint32, ctypes.POINTER(ctypes.c_size_t)]),
+    "aln_align_batch": (ctypes.c_int32, [ctypes.POINTER(aln_scoring_t), ctypes.c_int64, ctypes.c_void_p,
+                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                         ctypes.c_int64, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_void_p,
+                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
+    "aln_status_string": (ctypes.c_char_p, [ctypes.c_int32]),
+    "aln_version": (ctypes.c_char_p, []),
+}
+
+
+def lib():
+    """Loads libmialign.so (built by paper_2002_04561_amd.build); raises if it is missing."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libmialign.so is not built (run __graft_entry__.build() or "
+                               "python paper_2002_04561_amd/build.py); there is no CPU fallback")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def exported_symbols():
+    return list(_SIGNATURES)
+
+
+@dataclass
+class Scoring:
+    """aln_scoring_t: mode, alphabet, substitution table (or match/mismatch), signed gap open/extend."""
+
+    mode: int
+    alphabet_size: int
+    gap_open: int
+    gap_extend: int
+    match: int = 0
+    mismatch: int = 0
+    subst: Optional[np.ndarray] = None
+
+    def c(self) -> aln_scoring_t:
+        if self.subst is not None:
+            self._subst_buf = np.ascontiguousarray(self.subst, dtype=np.int8)
+            ptr = self._subst_buf.ctypes.data_as(ctypes.POINTER(ctypes.c_int8))
+        else:
+            ptr = ctypes.POINTER(ctypes.c_int8)()
+        return aln_scoring_t(self.mode, self.alphabet_size, ptr, self.match, self.mismatch, self.gap_open,
+                             self.gap_extend)
+
+
+def _ptr(t) -> Optional[int]:
+    if t is None:
+        return None
+    return int(t.data_ptr())
+
+
+def _stream_handle(stream) -> Optional[int]:
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    return int(stream.cuda_stream)
+
+
+def aln_batch_workspace_size(scoring: Scoring, n_pairs: int, max_n: int, max_m: int, flags: int) -> int:
+    out = ctypes.c_size_t(0)
+    sc = scoring.c()
+    st = lib().aln_batch_workspace_size(ctypes.byref(sc), n_pairs, max_n, max_m, flags, ctypes.byref(out))
+    if st != 0:
+        raise AlnError(st, "aln_batch_workspace_size")
+    return int(out.value)
+
+
+def aln_align_batch(scoring: Scoring, n_pairs: int, q, q_off, s, s_off, max_n: int, max_m: int, flags: int, out,
+                    cigar, cigar_off, workspace, workspace_bytes: int, stream=None) -> int:
+    """Same arguments as the C function; tensors are torch device tensors.  Returns the status code."""
+    sc = scoring.c()
+    return int(lib().aln_align_batch(ctypes.byref(sc), n_pairs, _ptr(q), _ptr(q_off), _ptr(s), _ptr(s_off), max_n,
+                                     max_m, flags, _ptr(out), _ptr(cigar), _ptr(cigar_off), _ptr(workspace),
+                                     workspace_bytes, _stream_handle(stream)))
+
+
+def aln_status_string(status: int) -> str:
+    return lib().aln_status_string(status).decode()
+
+
+def aln_version() -> str:
+    return lib().aln_version().decode()
+
+
+class BatchAligner:
+    """Owns the device buffers for repeated aln_align_batch calls over one set of device-resident pairs."""
+
+    def __init__(self, scoring: Scoring, q, q_off, s, s_off, max_n: int, max_m: int, flags: int = SCORE_ONLY,
+                 cigar_capacity=None, device="cuda"):
+        import torch
+        self.torch = torch
+        self.scoring = scoring
+        self.q, self.q_off, self.s, self.s_off = q, q_off, s, s_off
+        self.n_pairs = int(q_off.numel()) - 1
+        self.max_n, self.max_m, self.flags = int(max_n), int(max_m), int(flags)
+        self.out = torch.empty(self.n_pairs * 8, dtype=torch.int32, device=device)
+        self.cigar = self.cigar_off = None
+        if flags & TRACEBACK:
+            if cigar_capacity is None:
+                qo = q_off.to("cpu").numpy()
+                so = s_off.to("cpu").numpy()
+                cap = (qo[1:] - qo[:-1]) + (so[1:] - so[:-1])
+                cap = np.maximum(cap, 1)
+            else:
+                cap = np.asarray(cigar_capacity, dtype=np.int64)
+            coff = np.zeros(self.n_pairs + 1, dtype=np.int64)
+            np.cumsum(cap, out=coff[1:])
+            self.cigar_off = torch.from_numpy(coff).to(device)
+            self.cigar = torch.empty(max(int(coff[-1]), 1), dtype=torch.int32, device=device)
+        self.ws_bytes = aln_batch_workspace_size(scoring, self.n_pairs, self.max_n, self.max_m, self.flags)
+        self.workspace = torch.empty(max(self.ws_bytes, 256), dtype=torch.uint8, device=device)
+
+    def run(self, stream=None):
+        st = aln_align_batch(self.scoring, self.n_pairs, self.q, self.q_off, self.s, self.s_off, self.max_n,
+                             self.max_m, self.flags, self.out, self.cigar, self.cigar_off, self.workspace,
+                             self.ws_bytes, stream)
+        if st != 0:
+            raise AlnError(st, "aln_align_batch")
+
+    def results(self) -> np.ndarray:
+        return self.out.to("cpu").numpy().view(RESULT_DTYPE)
+
+    def cigars(self):
+        res = self.results()
+        cig = self.cigar.to("cpu").numpy().view(np.uint32)
+        coff = self.cigar_off.to("cpu").numpy()
+        out = []
+        for k in range(self.n_pairs):
+            L = int(res["cigar_len"][k])
+            w = cig[coff[k]:coff[k] + min(L, coff[k + 1] - coff[k])]
+            out.append([(int(x) >> 4, int(x) & 15) for x in w])
+        return out
+
+
+def to_device(workload, device="cuda"):
+    """Copies a synth.Workload's arrays to the device (torch tensors)."""
+    import torch
+    q = torch.from_numpy(np.ascontiguousarray(workload.q) if len(workload.q) else np.zeros(1, np.uint8)).to(device)
+    s = torch.from_numpy(np.ascontiguousarray(workload.s) if len(workload.s) else np.zeros(1, np.uint8)).to(device)
+    qo = torch.from_numpy(np.ascontiguousarray(workload.q_off)).to(device)
+    so = torch.from_numpy(np.ascontiguousarray(workload.s_off)).to(device)
+    return q, qo, s, so
+
+
+def scoring_of(workload) -> Scoring:
+    return Scoring(workload.mode, workload.alphabet_size, workload.gap_open, workload.gap_extend,
+                   match=workload.match or 0, mismatch=workload.mismatch or 0, subst=workload.subst)

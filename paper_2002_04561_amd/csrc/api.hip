@@ -1,0 +1,131 @@
+// C-ABI entry points of mialign: argument validation, workspace sizing and dispatch.
+#include <cstring>
+
+#include "internal.h"
+
+namespace mialign {
+
+int device_cu_count() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return -1;
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return -1;
+  return cus;
+}
+
+aln_status_t make_params(const aln_scoring_t* sc, KParams* kp) {
+  if (!sc || !kp) return ALN_E_INVALID;
+  if (sc->mode < ALN_GLOBAL || sc->mode > ALN_SEMIGLOBAL) return ALN_E_INVALID;
+  if (sc->alphabet_size < 2 || sc->alphabet_size > kMaxAlphabet) return ALN_E_ALPHABET;
+  if (sc->gap_open > 0 || sc->gap_extend >= 0) return ALN_E_SCORING;
+  if (sc->gap_open < -(1 << 16) || sc->gap_extend < -(1 << 16)) return ALN_E_SCORING;
+  std::memset(kp, 0, sizeof(*kp));
+  kp->mode = sc->mode;
+  kp->alphabet = sc->alphabet_size;
+  kp->go = sc->gap_open;
+  kp->ge = sc->gap_extend;
+  kp->goe = sc->gap_open + sc->gap_extend;
+  const int A = sc->alphabet_size;
+  int smax = -1000, smin = 1000;
+  if (sc->subst) {
+    kp->use_table = 1;
+    for (int a = 0; a < A; ++a)
+      for (int b = 0; b < A; ++b) {
+        const int v = sc->subst[a * A + b];
+        kp->sig[a * kMaxAlphabet + b] = (int8_t)v;
+        smax = v > smax ? v : smax;
+        smin = v < smin ? v : smin;
+      }
+    kp->match = 0;
+    kp->mismatch = 0;
+  } else {
+    if (sc->match > 127 || sc->match < -127 || sc->mismatch > 127 || sc->mismatch < -127) return ALN_E_SCORING;
+    kp->use_table = 0;
+    kp->match = sc->match;
+    kp->mismatch = sc->mismatch;
+    for (int a = 0; a < A; ++a)
+      for (int b = 0; b < A; ++b) kp->sig[a * kMaxAlphabet + b] = (int8_t)(a == b ? sc->match : sc->mismatch);
+    smax = sc->match > sc->mismatch ? sc->match : sc->mismatch;
+    smin = sc->match < sc->mismatch ? sc->match : sc->mismatch;
+  }
+  kp->sigma_max = smax;
+  kp->sigma_min = smin;
+  return ALN_OK;
+}
+
+// Every exact score of an n x m problem lies in [3*go + (n+m)*ge, min(n,m)*max(sigma_max, 0)];
+// the 32-bit lanes need both ends well inside +-2^29 (the pad letter scores -2^29).
+static bool fits_i32(const KParams& kp, int64_t max_n, int64_t max_m) {
+  const int64_t mn = max_n < max_m ? max_n : max_m;
+  const int64_t up = mn * (kp.sigma_max > 0 ? kp.sigma_max : 0);
+  const int64_t lo = 3 * (int64_t)kp.go + (max_n + max_m) * (int64_t)kp.ge;
+  const int64_t lim = (int64_t)1 << 28;
+  return up < lim && -lo < lim;
+}
+
+}  // namespace mialign
+
+using namespace mialign;
+
+extern "C" {
+
+const char* aln_version(void) { return "mialign 0.1 (gfx950)"; }
+
+const char* aln_status_string(aln_status_t st) {
+  switch (st) {
+    case ALN_OK:
+      return "ok";
+    case ALN_E_INVALID:
+      return "invalid argument";
+    case ALN_E_ALPHABET:
+      return "alphabet_size must be in 2..32";
+    case ALN_E_SCORING:
+      return "invalid scoring (gap_open > 0, gap_extend >= 0, or scores too large for exact integer lanes)";
+    case ALN_E_WORKSPACE:
+      return "workspace too small";
+    case ALN_E_DEVICE:
+      return "HIP device error";
+    case ALN_E_UNSUPPORTED:
+      return "unsupported combination";
+    default:
+      return "unknown status";
+  }
+}
+
+aln_status_t aln_batch_workspace_size(const aln_scoring_t* scoring, int64_t n_pairs, int64_t max_n, int64_t max_m,
+                                      uint32_t flags, size_t* bytes) {
+  if (!bytes || n_pairs < 0 || max_n < 0 || max_m < 0) return ALN_E_INVALID;
+  KParams kp;
+  aln_status_t st = make_params(scoring, &kp);
+  if (st != ALN_OK) return st;
+  if (!fits_i32(kp, max_n, max_m)) return ALN_E_SCORING;
+  BatchPlan pl;
+  st = plan_batch_i32(kp, n_pairs, max_n, max_m, (flags & ALN_TRACEBACK) != 0, &pl);
+  if (st != ALN_OK) return st;
+  *bytes = pl.total_bytes;
+  return ALN_OK;
+}
+
+aln_status_t aln_align_batch(const aln_scoring_t* scoring, int64_t n_pairs, const uint8_t* q, const int64_t* q_off,
+                             const uint8_t* s, const int64_t* s_off, int64_t max_n, int64_t max_m, uint32_t flags,
+                             aln_result_t* out, uint32_t* cigar, const int64_t* cigar_off, void* workspace,
+                             size_t workspace_bytes, hipStream_t stream) {
+  if (n_pairs < 0 || max_n < 0 || max_m < 0) return ALN_E_INVALID;
+  if (flags & ~(ALN_TRACEBACK | ALN_FORCE_INT32 | ALN_FORCE_INT16)) return ALN_E_INVALID;
+  KParams kp;
+  aln_status_t st = make_params(scoring, &kp);
+  if (st != ALN_OK) return st;
+  if (n_pairs == 0) return ALN_OK;
+  if (!q_off || !s_off || !out) return ALN_E_INVALID;
+  if ((!q && max_n > 0) || (!s && max_m > 0)) return ALN_E_INVALID;
+  const bool tb = (flags & ALN_TRACEBACK) != 0;
+  if (tb && (!cigar || !cigar_off)) return ALN_E_INVALID;
+  if (!fits_i32(kp, max_n, max_m)) return ALN_E_SCORING;
+  BatchPlan pl;
+  st = plan_batch_i32(kp, n_pairs, max_n, max_m, tb, &pl);
+  if (st != ALN_OK) return st;
+  if (pl.total_bytes > 0 && (!workspace || workspace_bytes < pl.total_bytes)) return ALN_E_WORKSPACE;
+  return launch_batch_i32(kp, pl, q, q_off, s, s_off, tb, out, cigar, cigar_off, workspace, stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,401 @@
+// Inter-sequence batch kernel, 32-bit lanes.
+//
+// One lane aligns one pair (inter-sequence parallelism).  The lane relaxes its
+// DP matrix in strips of R query rows held in registers, sweeping the subject
+// column by column; the bottom row (H, E) of a strip is kept in a per-wave row
+// buffer in the workspace, interleaved [column][lane] so the 64 lanes of a
+// wave touch one contiguous 512-byte line per column.  This is the strip
+// relaxation of AnySeq Sec. III-A (a strip needs its top row computed before
+// and publishes its last row) applied per lane.
+//
+// With traceback, every cell also records a 4-bit predecessor code (the
+// NextStep.predc of Sec. III-B extended by the two gap-open bits of the affine
+// model): bits 0-1 = source of H (0 diagonal, 1 E, 2 F, 3 local zero),
+// bit 2 = E(i,j) opened from H(i-1,j), bit 3 = F(i,j) opened from H(i,j-1).
+// The R codes of one column of a strip form one 32-bit word.  The same wave
+// then walks each pair back from its optimum and writes the CIGAR.
+#include "internal.h"
+
+namespace mialign {
+namespace {
+
+constexpr int R = 8;
+constexpr int kWavesPerBlock = 4;
+constexpr int kBlock = 64 * kWavesPerBlock;
+constexpr int kWavesPerCU = 8;
+
+__device__ __forceinline__ int wave_max_i32(int v) {
+  for (int o = 32; o >= 1; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// Walks one pair back from its optimum (i, j) and writes its CIGAR (in reverse, then flipped).
+template <int MODE>
+__device__ void walk_back(const uint32_t* __restrict__ dirs, int lane, int64_t max_m, int i, int j, uint32_t* cig,
+                          int64_t cap, int* q_begin, int* s_begin, int* n_runs) {
+  int state = 0;  // 0 = H, 1 = E, 2 = F
+  int64_t runs = 0;
+  uint32_t cur_op = 0xffu, cur_len = 0;
+  auto push = [&](uint32_t op) {
+    if (op == cur_op) {
+      ++cur_len;
+      return;
+    }
+    if (cur_len) {
+      if (runs < cap) cig[runs] = (cur_len << 4) | cur_op;
+      ++runs;
+    }
+    cur_op = op;
+    cur_len = 1;
+  };
+  auto code = [&](int ii, int jj) -> uint32_t {
+    const uint32_t w = dirs[((size_t)((ii - 1) / R) * (size_t)max_m + (size_t)(jj - 1)) * 64 + lane];
+    return (w >> (4 * ((ii - 1) % R))) & 15u;
+  };
+  for (;;) {
+    if (state == 0) {
+      if (i == 0 || j == 0) {
+        if (MODE == ALN_GLOBAL) {
+          while (j > 0) {
+            push(ALN_CIGAR_D);
+            --j;
+          }
+          while (i > 0) {
+            push(ALN_CIGAR_I);
+            --i;
+          }
+        }
+        break;
+      }
+      const uint32_t hs = code(i, j) & 3u;
+      if (hs == 3u) break;
+      if (hs == 0u) {
+        push(ALN_CIGAR_M);
+        --i;
+        --j;
+      } else {
+        state = (int)hs;
+      }
+    } else if (state == 1) {
+      const uint32_t c = code(i, j);
+      push(ALN_CIGAR_I);
+      if (c & 4u) state = 0;
+      --i;
+      if (i == 0) state = 0;
+    } else {
+      const uint32_t c = code(i, j);
+      push(ALN_CIGAR_D);
+      if (c & 8u) state = 0;
+      --j;
+      if (j == 0) state = 0;
+    }
+  }
+  if (cur_len) {
+    if (runs < cap) cig[runs] = (cur_len << 4) | cur_op;
+    ++runs;
+  }
+  if (runs <= cap) {
+    for (int64_t a = 0, b = runs - 1; a < b; ++a, --b) {
+      const uint32_t t = cig[a];
+      cig[a] = cig[b];
+      cig[b] = t;
+    }
+  }
+  *q_begin = i;
+  *s_begin = j;
+  *n_runs = (int)runs;
+}
+
+template <int MODE, bool AFFINE, bool TB>
+__global__ __launch_bounds__(kBlock) void batch_i32_kernel(
+    const KParams P, const uint8_t* __restrict__ q, const int64_t* __restrict__ q_off, const uint8_t* __restrict__ s,
+    const int64_t* __restrict__ s_off, int64_t n_pairs, int64_t max_n, int64_t max_m, aln_result_t* __restrict__ out,
+    uint32_t* __restrict__ cigar, const int64_t* __restrict__ cigar_off, char* __restrict__ ws, size_t slab_bytes,
+    size_t rowbuf_bytes) {
+  __shared__ int32_t tab[kTab * kTab];
+  for (int k = threadIdx.x; k < kTab * kTab; k += blockDim.x) {
+    const int a = k / kTab, b = k % kTab;
+    int32_t v;
+    if (a >= P.alphabet || b >= P.alphabet)
+      v = -kBig32;
+    else
+      v = P.use_table ? (int32_t)P.sig[a * kMaxAlphabet + b] : (a == b ? P.match : P.mismatch);
+    tab[k] = v;
+  }
+  __syncthreads();
+
+  const int lane = threadIdx.x & 63;
+  const int64_t wave = (int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+  const int64_t n_waves = (int64_t)gridDim.x * kWavesPerBlock;
+  char* slab = ws + wave * slab_bytes;
+  int2* __restrict__ rowbuf = reinterpret_cast<int2*>(slab);
+  uint32_t* __restrict__ dirs = reinterpret_cast<uint32_t*>(slab + rowbuf_bytes);
+  const int64_t groups = (n_pairs + 63) / 64;
+  const int32_t go = P.go, ge = P.ge, goe = P.goe;
+
+  for (int64_t g = wave; g < groups; g += n_waves) {
+    const int64_t p = g * 64 + lane;
+    const bool active = p < n_pairs;
+    int64_t qb = 0, sb = 0;
+    int n = 0, m = 0;
+    uint32_t flags = 0;
+    if (active) {
+      qb = q_off[p];
+      sb = s_off[p];
+      const int64_t nn = q_off[p + 1] - qb, mm = s_off[p + 1] - sb;
+      if (nn > max_n || mm > max_m || nn < 0 || mm < 0) {
+        flags |= ALN_RES_TOO_LONG;
+      } else {
+        n = (int)nn;
+        m = (int)mm;
+      }
+    }
+    const int nmax = wave_max_i32(n), mmax = wave_max_i32(m);
+    const int strips = (nmax + R - 1) / R;
+
+    // optimum bookkeeping
+    int32_t best = 0;
+    int bi = 0, bj = 0;
+    if (MODE == ALN_SEMIGLOBAL) bj = m;   // first candidate in row-major order: (0, m)
+    int32_t brow = 0;                     // semi: best of row n so far, starting at (n, 0)
+    int browj = 0;
+    int32_t hfinal = 0;                   // global: H(n, m)
+    bool bad = false;
+
+    for (int k = 0; k < strips; ++k) {
+      const int i0 = k * R;  // this strip holds rows i0+1 .. i0+R
+      int qcb[R];
+      int32_t hl[R], f[R], bv[R], cap[R];
+      int bjr[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int i = i0 + 1 + r;
+        int c = kPad;
+        if (i <= n) {
+          c = q[qb + i - 1];
+          if (c >= P.alphabet) {
+            bad = true;
+            c = kPad;
+          }
+        }
+        qcb[r] = c * kTab;
+        hl[r] = (MODE == ALN_GLOBAL) ? go + i * ge : 0;
+        f[r] = kNeg32;
+        bv[r] = kNeg32;
+        bjr[r] = 0;
+        cap[r] = 0;
+      }
+      int32_t hdiag = (MODE == ALN_GLOBAL && i0 > 0) ? go + i0 * ge : 0;  // H(i0, 0)
+      const bool has_n = (i0 < n) && (n <= i0 + R);
+      const int rn = n - 1 - i0;
+      for (int j = 1; j <= mmax; ++j) {
+        int c = kPad;
+        if (j <= m) {
+          c = s[sb + j - 1];
+          if (c >= P.alphabet) {
+            bad = true;
+            c = kPad;
+          }
+        }
+        int32_t hup, eup;
+        if (k == 0) {
+          hup = (MODE == ALN_GLOBAL) ? go + j * ge : 0;
+          eup = kNeg32;
+        } else {
+          const int2 v = rowbuf[(size_t)j * 64 + lane];
+          hup = v.x;
+          eup = v.y;
+        }
+        int32_t hd = hdiag;
+        hdiag = hup;
+        uint32_t word = 0;
+        int32_t hn = 0;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const int32_t hlo = hl[r];
+          const int32_t e = AFFINE ? max(eup + ge, hup + goe) : hup + ge;
+          const int32_t ff = AFFINE ? max(f[r] + ge, hlo + goe) : hlo + ge;
+          const int32_t d = hd + tab[qcb[r] + c];
+          int32_t h = max(d, max(e, ff));
+          if (MODE == ALN_LOCAL) h = max(h, 0);
+          if (TB) {
+            uint32_t src;
+            if (MODE == ALN_LOCAL && h == 0)
+              src = 3u;
+            else if (d == h)
+              src = 0u;
+            else if (e == h)
+              src = 1u;
+            else
+              src = 2u;
+            const uint32_t eo = AFFINE ? (uint32_t)(hup + goe == e) : 1u;
+            const uint32_t fo = AFFINE ? (uint32_t)(hlo + goe == ff) : 1u;
+            word |= (src | (eo << 2) | (fo << 3)) << (4 * r);
+          }
+          if (MODE == ALN_LOCAL) {
+            if (h > bv[r]) {
+              bv[r] = h;
+              bjr[r] = j;
+            }
+          } else {
+            if (j == m) cap[r] = h;
+            if (MODE == ALN_SEMIGLOBAL && r == rn) hn = h;
+          }
+          f[r] = ff;
+          hl[r] = h;
+          hd = hlo;
+          hup = h;
+          eup = e;
+        }
+        if (k + 1 < strips) rowbuf[(size_t)j * 64 + lane] = make_int2(hup, eup);
+        if (TB) dirs[((size_t)k * (size_t)max_m + (size_t)(j - 1)) * 64 + lane] = word;
+        if (MODE == ALN_SEMIGLOBAL && has_n && j <= m && hn > brow) {
+          brow = hn;
+          browj = j;
+        }
+      }
+      // merge this strip's rows into the optimum, in row order
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int i = i0 + 1 + r;
+        if (MODE == ALN_LOCAL) {
+          if (bv[r] > best) {
+            best = bv[r];
+            bi = i;
+            bj = bjr[r];
+          }
+        } else if (MODE == ALN_SEMIGLOBAL) {
+          if (i < n && cap[r] > best) {
+            best = cap[r];
+            bi = i;
+            bj = m;
+          }
+        } else {
+          if (i == n) hfinal = cap[r];
+        }
+      }
+    }
+
+    if (MODE == ALN_SEMIGLOBAL) {
+      if (n == 0 || m == 0) {
+        best = 0;
+        bi = 0;
+        bj = 0;
+      } else if (brow > best) {
+        best = brow;
+        bi = n;
+        bj = browj;
+      }
+    } else if (MODE == ALN_GLOBAL) {
+      bi = n;
+      bj = m;
+      if (n == 0 || m == 0)
+        best = (n + m > 0) ? go + (n + m) * ge : 0;
+      else
+        best = hfinal;
+    }
+
+    if (!active) continue;
+    aln_result_t res;
+    res.score = best;
+    res.q_begin = -1;
+    res.q_end = bi;
+    res.s_begin = -1;
+    res.s_end = bj;
+    res.cigar_len = 0;
+    res.reserved = 0;
+    if (bad) flags |= ALN_RES_BAD_CODE;
+    if (flags) {
+      res.score = 0;
+      res.q_end = 0;
+      res.s_end = 0;
+    } else if (TB) {
+      const int64_t c0 = cigar_off[p];
+      const int64_t capw = cigar_off[p + 1] - c0;
+      int qbeg, sbeg, runs;
+      walk_back<MODE>(dirs, lane, max_m, bi, bj, cigar + c0, capw, &qbeg, &sbeg, &runs);
+      res.q_begin = qbeg;
+      res.s_begin = sbeg;
+      res.cigar_len = runs;
+      if (runs > capw) flags |= ALN_RES_CIGAR_TRUNC;
+    }
+    res.flags = flags;
+    out[p] = res;
+  }
+}
+
+template <int MODE, bool AFFINE, bool TB>
+void launch_one(const KParams& kp, const BatchPlan& pl, const uint8_t* q, const int64_t* q_off, const uint8_t* s,
+                const int64_t* s_off, aln_result_t* out, uint32_t* cigar, const int64_t* cigar_off, void* ws,
+                hipStream_t stream) {
+  const size_t slab = pl.rowbuf_bytes + pl.dirs_bytes;
+  const int blocks = (pl.n_waves + kWavesPerBlock - 1) / kWavesPerBlock;
+  hipLaunchKernelGGL((batch_i32_kernel<MODE, AFFINE, TB>), dim3(blocks), dim3(kBlock), 0, stream, kp, q, q_off, s,
+                     s_off, pl.n_pairs, pl.max_n, pl.max_m, out, cigar, cigar_off, static_cast<char*>(ws), slab,
+                     pl.rowbuf_bytes);
+}
+
+template <int MODE>
+void launch_mode(const KParams& kp, const BatchPlan& pl, const uint8_t* q, const int64_t* q_off, const uint8_t* s,
+                 const int64_t* s_off, bool tb, aln_result_t* out, uint32_t* cigar, const int64_t* cigar_off,
+                 void* ws, hipStream_t stream) {
+  const bool affine = kp.go != 0;
+  if (affine) {
+    if (tb)
+      launch_one<MODE, true, true>(kp, pl, q, q_off, s, s_off, out, cigar, cigar_off, ws, stream);
+    else
+      launch_one<MODE, true, false>(kp, pl, q, q_off, s, s_off, out, cigar, cigar_off, ws, stream);
+  } else {
+    if (tb)
+      launch_one<MODE, false, true>(kp, pl, q, q_off, s, s_off, out, cigar, cigar_off, ws, stream);
+    else
+      launch_one<MODE, false, false>(kp, pl, q, q_off, s, s_off, out, cigar, cigar_off, ws, stream);
+  }
+}
+
+size_t round256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+}  // namespace
+
+aln_status_t plan_batch_i32(const KParams& kp, int64_t n_pairs, int64_t max_n, int64_t max_m, bool traceback,
+                            BatchPlan* plan) {
+  (void)kp;
+  BatchPlan pl{};
+  pl.n_pairs = n_pairs;
+  pl.max_n = max_n;
+  pl.max_m = max_m;
+  pl.strips = (int32_t)((max_n + R - 1) / R);
+  const int64_t groups = (n_pairs + 63) / 64;
+  const int cus = device_cu_count();
+  if (cus <= 0) return ALN_E_DEVICE;
+  int64_t waves = (int64_t)cus * kWavesPerCU;
+  if (groups < waves) waves = groups;
+  if (waves < 1) waves = 1;
+  waves = (waves + kWavesPerBlock - 1) / kWavesPerBlock * kWavesPerBlock;  // every launched wave owns a slab
+  pl.n_waves = (int32_t)waves;
+  pl.rowbuf_bytes = round256((size_t)(max_m + 1) * 64 * sizeof(int2));
+  pl.dirs_bytes = traceback ? round256((size_t)pl.strips * (size_t)max_m * 64 * sizeof(uint32_t)) : 0;
+  pl.total_bytes = (size_t)pl.n_waves * (pl.rowbuf_bytes + pl.dirs_bytes);
+  *plan = pl;
+  return ALN_OK;
+}
+
+aln_status_t launch_batch_i32(const KParams& kp, const BatchPlan& pl, const uint8_t* q, const int64_t* q_off,
+                              const uint8_t* s, const int64_t* s_off, bool tb, aln_result_t* out, uint32_t* cigar,
+                              const int64_t* cigar_off, void* ws, hipStream_t stream) {
+  if (pl.n_pairs == 0) return ALN_OK;
+  switch (kp.mode) {
+    case ALN_GLOBAL:
+      launch_mode<ALN_GLOBAL>(kp, pl, q, q_off, s, s_off, tb, out, cigar, cigar_off, ws, stream);
+      break;
+    case ALN_LOCAL:
+      launch_mode<ALN_LOCAL>(kp, pl, q, q_off, s, s_off, tb, out, cigar, cigar_off, ws, stream);
+      break;
+    default:
+      launch_mode<ALN_SEMIGLOBAL>(kp, pl, q, q_off, s, s_off, tb, out, cigar, cigar_off, ws, stream);
+      break;
+  }
+  return hipGetLastError() == hipSuccess ? ALN_OK : ALN_E_DEVICE;
+}
+
+}  // namespace mialign

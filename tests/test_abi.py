@@ -1,0 +1,51 @@
+"""The C-ABI library loads and exports every function include/mialign.h declares (no GPU calls)."""
+import ctypes
+import os
+import re
+
+import paper_2002_04561_amd as aln
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    names = []
+    for fn in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if not fn.endswith(".h"):
+            continue
+        txt = open(os.path.join(ROOT, "include", fn)).read()
+        txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+        names += re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\**\s+\**(aln_[a-z0-9_]+)\s*\(", txt, re.M)
+    return sorted(set(names))
+
+
+def test_header_declares_entry_points():
+    d = _declared()
+    for name in ("aln_align_batch", "aln_batch_workspace_size", "aln_status_string", "aln_version"):
+        assert name in d
+
+
+def test_library_exports_every_declared_symbol():
+    L = ctypes.CDLL(aln.LIB_PATH)
+    for name in _declared():
+        assert hasattr(L, name), name
+    for name in aln.exported_symbols():
+        assert name in _declared(), name
+
+
+def test_status_strings_and_version():
+    assert "invalid" in aln.aln_status_string(-1)
+    assert aln.aln_status_string(0) == "ok"
+    assert "gfx950" in aln.aln_version()
+
+
+def test_scoring_validation_on_host():
+    """Invalid scoring is rejected before any device work (the size query touches no device memory)."""
+    bad = [aln.Scoring(0, 1, 0, -1, 1, -1), aln.Scoring(0, 33, 0, -1, 1, -1), aln.Scoring(0, 4, 1, -1, 1, -1),
+           aln.Scoring(0, 4, 0, 0, 1, -1), aln.Scoring(5, 4, 0, -1, 1, -1)]
+    expect = [-2, -2, -3, -3, -1]
+    for sc, e in zip(bad, expect):
+        out = ctypes.c_size_t(0)
+        c = sc.c()
+        st = aln.lib().aln_batch_workspace_size(ctypes.byref(c), 10, 100, 100, 0, ctypes.byref(out))
+        assert st == e, (sc, st)

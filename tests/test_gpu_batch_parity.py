@@ -1,0 +1,90 @@
+"""GPU parity of aln_align_batch against the oracle: bit-exact scores, end cells, begin cells and CIGARs."""
+import itertools
+
+import numpy as np
+import pytest
+
+import synth
+from helpers import compare, run_gpu, run_oracle
+
+pytestmark = pytest.mark.gpu
+
+PROT = synth.protein_sigma(np.random.default_rng(11))
+
+SCHEMES = {
+    # name: (alphabet, match, mismatch, subst, gap_open, gap_extend)
+    "dna_linear": (4, 2, -1, None, 0, -1),
+    "dna_affine": (4, 1, -4, None, -5, -2),
+    "prot_affine": (20, None, None, PROT, -11, -1),
+    "prot_linear": (20, None, None, PROT, 0, -4),
+}
+
+
+def _workload(seed, n_pairs, nmin, nmax, mode, scheme, related=0.5, mmin=None, mmax=None):
+    A, ma, mi, sub, go, ge = SCHEMES[scheme]
+    return synth.random_pairs(seed, n_pairs, nmin, nmax, A, mode, go, ge, match=ma, mismatch=mi, subst=sub,
+                              related=related, mmin=mmin, mmax=mmax)
+
+
+@pytest.mark.parametrize("mode", [0, 1, 2], ids=["global", "local", "semi"])
+@pytest.mark.parametrize("scheme", list(SCHEMES))
+@pytest.mark.parametrize("tb", [False, True], ids=["score", "traceback"])
+def test_random_ragged(gpu, mode, scheme, tb):
+    import paper_2002_04561_amd as aln
+    w = _workload(100 + mode * 10 + len(scheme), 150, 0, 300, mode, scheme)
+    flags = aln.TRACEBACK if tb else aln.SCORE_ONLY
+    gres, gcig = run_gpu(w, flags)
+    ores, ocig = run_oracle(w, tb)
+    bad = compare(w, gres, gcig, ores, ocig, "%d/%s/%s" % (mode, scheme, tb))
+    assert not bad, "\n".join(bad[:10])
+
+
+@pytest.mark.parametrize("mode", [0, 1, 2], ids=["global", "local", "semi"])
+@pytest.mark.parametrize("go", [0, -2])
+def test_exhaustive_binary(gpu, mode, go):
+    """All pairs of binary sequences of length 0..4 (31 x 31 pairs) -- ties everywhere."""
+    import paper_2002_04561_amd as aln
+    seqs = [np.array(t, dtype=np.uint8) for L in range(5) for t in itertools.product([0, 1], repeat=L)]
+    qs = [a for a in seqs for _ in seqs]
+    ss = [b for _ in seqs for b in seqs]
+    q, qo = synth.pack(qs)
+    s, so = synth.pack(ss)
+    w = synth.Workload("binary", mode, 2, go, -1, q, qo, s, so, match=1, mismatch=-1)
+    gres, gcig = run_gpu(w, aln.TRACEBACK)
+    ores, ocig = run_oracle(w, True)
+    bad = compare(w, gres, gcig, ores, ocig, "binary")
+    assert not bad, "\n".join(bad[:10])
+
+
+@pytest.mark.parametrize("mode", [0, 1, 2], ids=["global", "local", "semi"])
+def test_edge_shapes(gpu, mode):
+    import paper_2002_04561_amd as aln
+    rng = np.random.default_rng(5)
+    shapes = [(0, 0), (0, 5), (5, 0), (1, 1), (1, 2000), (2000, 1), (7, 900), (900, 7), (64, 64), (65, 63),
+              (8, 8), (9, 8), (16, 1), (1, 16)]
+    qs = [rng.integers(0, 4, a, dtype=np.uint8) for a, _ in shapes]
+    ss = [rng.integers(0, 4, b, dtype=np.uint8) for _, b in shapes]
+    q, qo = synth.pack(qs)
+    s, so = synth.pack(ss)
+    w = synth.Workload("edges", mode, 4, -3, -1, q, qo, s, so, match=2, mismatch=-3)
+    for flags in (aln.SCORE_ONLY, aln.TRACEBACK):
+        gres, gcig = run_gpu(w, flags)
+        ores, ocig = run_oracle(w, bool(flags))
+        bad = compare(w, gres, gcig, ores, ocig, "edges")
+        assert not bad, "\n".join(bad[:10])
+
+
+def test_bad_codes_flagged(gpu):
+    import paper_2002_04561_amd as aln
+    qs = [np.array([0, 1, 2, 3], np.uint8), np.array([0, 1, 9, 3], np.uint8), np.array([1, 1], np.uint8)]
+    ss = [np.array([0, 1, 2], np.uint8), np.array([0, 1], np.uint8), np.array([1, 200], np.uint8)]
+    q, qo = synth.pack(qs)
+    s, so = synth.pack(ss)
+    w = synth.Workload("bad", 1, 4, -3, -1, q, qo, s, so, match=2, mismatch=-3)
+    gres, gcig = run_gpu(w, aln.TRACEBACK)
+    assert int(gres["flags"][0]) & aln.RES_BAD_CODE == 0
+    assert int(gres["flags"][1]) & aln.RES_BAD_CODE
+    assert int(gres["flags"][2]) & aln.RES_BAD_CODE
+    ores, ocig = run_oracle(w, True)
+    bad = compare(w, gres, gcig, ores, ocig, "bad")
+    assert not bad, "\n".join(bad)
