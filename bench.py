@@ -1,0 +1,218 @@
+#!/usr/bin/env python3
+"""Benchmark of the alignment hot path on one MI355X: GCUPS, bit-exact against the oracle.
+
+  python bench.py [--steps K] [--warmup W] [--workload NAME] [--no-cpu-baseline]
+
+One step is one call of the library on one batch of synthetic, device-resident input (every pass of
+the path the workload needs: planning, the DP relaxation, optimum selection, 16/32-bit redo, and the
+traceback when the workload asks for CIGARs).  Prints one JSON line.
+
+Workloads (synth/__init__.py has the recipes):
+  long     1 pair 262144 x 262144 DNA, local affine (-3/-1, +2/-3), score + end cell       [default]
+  reads    1,048,576 read/window pairs, semi-global affine (-5/-2, +1/-4), CIGAR for every pair
+  protein  65,536 protein pairs, lengths log-uniform 64..16384, local affine (-11/-1), score-only
+  nw1k     1 pair 1000 x 1000 DNA, global linear (+2/-1, gap -1), CIGAR
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Peak integer VALU rate of MI355X: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz = 39.32 T lane-ops/s;
+# packed 16-bit instructions do two lane-ops each (78.64 T).
+PEAK_I32_TOPS = 256 * 64 * 2.4e9 / 1e12
+PEAK_I16_TOPS = 2 * PEAK_I32_TOPS
+
+# Algorithmic integer ops per DP cell (each 2-input add/sub/max and the substitution lookup count 1):
+# linear: sigma, diagonal add, up+g, left+g, max3 (2) = 5 ... as in Eqs. (1)-(5).
+OPS_PER_CELL = {("global", "linear"): 5, ("semiglobal", "linear"): 5, ("local", "linear"): 7,
+                ("global", "affine"): 10, ("semiglobal", "affine"): 10, ("local", "affine"): 12}
+MODE_NAME = {0: "global", 1: "local", 2: "semiglobal"}
+
+
+def make_workload(name, pairs=None):
+    import synth
+    if name == "long":
+        return synth.long_dna_local()
+    if name == "reads":
+        return synth.reads_semiglobal(n_pairs=pairs or (1 << 20))
+    if name == "protein":
+        return synth.protein_uneven(n_pairs=pairs or 65536)
+    if name == "nw1k":
+        return synth.long_dna_global_1k()
+    raise SystemExit("unknown workload %s" % name)
+
+
+def _oracle_scoring(w):
+    import oracle
+    return oracle.Scoring.matrix(w.mode, w.sigma_table(), w.gap_open, w.gap_extend)
+
+
+def run_cpu_baseline(w, budget_s=15.0):
+    """The oracle as it stands, on a bounded sample of the workload, on the host's cores."""
+    import oracle
+    threads = len(os.sched_getaffinity(0))
+    sc = _oracle_scoring(w)
+    n, m = w.lengths()
+    cells = n.astype(np.int64) * m.astype(np.int64)
+    if w.n_pairs == 1:
+        # one long pair: the oracle runs on one thread; sample = the first rows of the matrix
+        a, b = w.pair(0)
+        rows = max(1, min(len(a), int(1e10 / max(len(b), 1))))
+        t0 = time.perf_counter()
+        oracle.align(sc, a[:rows], b, traceback=w.traceback, impl="affine" if w.traceback else "linspace")
+        dt = time.perf_counter() - t0
+        return {"value": rows * len(b) / dt / 1e9, "unit": "GCUPS", "cores": 1, "kind": "oracle",
+                "sample": "first %d rows x %d columns of the pair (%.1f s)" % (rows, len(b), dt)}
+    # batches: pairs in order until the measured time reaches the budget (calibrated on a small prefix)
+    k = min(w.n_pairs, 64)
+    t0 = time.perf_counter()
+    sub = w.subset(np.arange(k))
+    oracle.align_batch(sc, sub.q, sub.q_off, sub.s, sub.s_off, traceback=w.traceback, threads=threads)
+    dt = max(time.perf_counter() - t0, 1e-3)
+    rate = cells[:k].sum() / dt
+    target = rate * budget_s
+    csum = np.cumsum(cells)
+    k2 = int(min(w.n_pairs, max(k, np.searchsorted(csum, target))))
+    sub = w.subset(np.arange(k2))
+    t0 = time.perf_counter()
+    oracle.align_batch(sc, sub.q, sub.q_off, sub.s, sub.s_off, traceback=w.traceback, threads=threads)
+    dt = time.perf_counter() - t0
+    return {"value": float(csum[k2 - 1]) / dt / 1e9, "unit": "GCUPS", "cores": threads, "kind": "oracle",
+            "sample": "first %d of %d pairs, %.3g cells, %s (%.1f s)" % (
+                k2, w.n_pairs, float(csum[k2 - 1]), "with traceback" if w.traceback else "score-only", dt)}
+
+
+def sample_indices(w, count=64, seed=0):
+    rng = np.random.default_rng(seed)
+    return rng.choice(w.n_pairs, size=min(count, w.n_pairs), replace=False)
+
+
+def spot_check(w, res, cigars, idx):
+    """Compares sampled pairs bit-exactly with the oracle (one by one)."""
+    import oracle
+    sc = _oracle_scoring(w)
+    for k in idx:
+        a, b = w.pair(int(k))
+        if w.n_pairs == 1 and len(a) * len(b) > 4e8:
+            g = os.path.join(ROOT, "tests", "golden", "long_local_262144.json")
+            if w.name == "long_dna_local_262144" and os.path.exists(g):
+                gold = json.load(open(g))
+                ok = (int(res["score"][0]), int(res["q_end"][0]), int(res["s_end"][0])) == \
+                     (gold["score"], gold["q_end"], gold["s_end"])
+                return ("bit-exact vs the stored oracle value" if ok else "MISMATCH vs the stored oracle value")
+            return "not checked (pair too large for a one-by-one oracle run)"
+        if w.traceback:
+            r = oracle.align(sc, a, b, traceback=True)
+            g = (int(res["score"][k]), int(res["q_begin"][k]), int(res["q_end"][k]), int(res["s_begin"][k]),
+                 int(res["s_end"][k]), cigars[k])
+            o = (r.score, r.q_begin, r.q_end, r.s_begin, r.s_end, r.cigar)
+        else:
+            r = oracle.align(sc, a, b, impl="linspace")
+            g = (int(res["score"][k]), int(res["q_end"][k]), int(res["s_end"][k]))
+            o = (r.score, r.q_end, r.s_end)
+        if g != o:
+            return "MISMATCH pair %d" % k
+    return "bit-exact on %d sampled pairs" % len(idx)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="reads", choices=["long", "reads", "protein", "nw1k"])
+    ap.add_argument("--pairs", type=int, default=None, help="override the pair count of a batch workload")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-check", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (see DESIGN.md for how the "
+              "work would shard)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2002_04561_amd as aln
+
+    def log(*a):
+        print("[bench]", *a, file=sys.stderr, flush=True)
+
+    torch.cuda.set_device(0)
+    t0 = time.time()
+    w = make_workload(args.workload, args.pairs)
+    n, m = w.lengths()
+    cells = w.cells()
+    log("workload %s: %d pairs, %.4g cells, generated in %.1f s" % (w.name, w.n_pairs, cells, time.time() - t0))
+    stream = torch.cuda.Stream()
+    flags = aln.TRACEBACK if w.traceback else aln.SCORE_ONLY
+    long_path = (w.n_pairs == 1 and not w.traceback)
+    with torch.cuda.stream(stream):
+        q, qo, s, so = aln.to_device(w)
+        if long_path:
+            ba = aln.LongAligner(aln.scoring_of(w), q[:int(n[0])], s[:int(m[0])], flags)
+        else:
+            ba = aln.BatchAligner(aln.scoring_of(w), q, qo, s, so, int(n.max()), int(m.max()), flags)
+    torch.cuda.synchronize()
+    log("device buffers ready; workspace %.3g GB" % (ba.ws_bytes / 1e9))
+    for _ in range(args.warmup):
+        ba.run(stream)
+    torch.cuda.synchronize()
+    aln.aln_profile_enable(True)
+    aln.aln_profile_reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ba.run(stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = aln.aln_profile_read()
+    aln.aln_profile_enable(False)
+    ms = (t1 - t0) * 1e3 / args.steps
+    gcups = cells / (ms * 1e-3) / 1e9
+    log("%.3f ms/step, %.1f GCUPS; kernels %s" % (ms, gcups, prof))
+
+    res = ba.result().reshape(1) if long_path else ba.results()
+    idx = sample_indices(w)
+    cigars = ba.cigars(idx) if w.traceback else None
+    check = "skipped" if args.no_check else spot_check(w, res, cigars, idx)
+    log("parity:", check)
+
+    gap = "linear" if w.gap_open == 0 else "affine"
+    opc = OPS_PER_CELL[(MODE_NAME[w.mode], gap)]
+    dom = max(prof.items(), key=lambda kv: kv[1][1]) if prof else None
+    dtype = "int32"
+    peak = PEAK_I32_TOPS if dtype == "int32" else PEAK_I16_TOPS
+    roof = None
+    if dom:
+        per_launch_ms = dom[1][1] / max(dom[1][0], 1)
+        launches_per_step = dom[1][0] / args.steps
+        cells_per_launch = cells / max(launches_per_step, 1e-9)
+        achieved = opc * cells_per_launch / (per_launch_ms * 1e-3) / 1e12
+        roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 2), "unit": "Tops/s",
+                "frac": round(achieved / peak, 4), "traffic": None, "kernel": dom[0],
+                "kernel_ms": round(per_launch_ms, 4), "ops_per_cell": opc}
+    out = {
+        "metric": "GCUPS (batched vs plain, bit-exact) on one MI355X; p50/p99 request latency",
+        "value": round(gcups, 2), "unit": "GCUPS", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": dtype, "data": "synthetic (seeded generator, synth/__init__.py)",
+        "config": {"workload": w.name, "pairs": w.n_pairs, "cells": cells, "mode": MODE_NAME[w.mode], "gap": gap,
+                   "gap_open": w.gap_open, "gap_extend": w.gap_extend, "traceback": bool(w.traceback)},
+        "parity": check,
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        log("timing the oracle on a host sample ...")
+        out["cpu_baseline"] = run_cpu_baseline(w)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

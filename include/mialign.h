@@ -96,6 +96,7 @@ typedef struct {
 #define ALN_RES_CIGAR_TRUNC 2u /* CIGAR capacity too small; cigar_len holds the required count */
 #define ALN_RES_BAD_CODE 4u    /* a sequence code >= alphabet_size; no score computed */
 #define ALN_RES_TOO_LONG 8u    /* n > max_n or m > max_m (the bounds the workspace was sized for) */
+#define ALN_RES_DEVICE_ERROR 16u /* a bounded device-side wait gave up; the result is not valid */
 
 /* CIGAR words: (run_length << 4) | op, op 0 = M (match or mismatch), 1 = I (query letter
  * against a gap), 2 = D (subject letter against a gap), in alignment order. */
@@ -104,15 +105,20 @@ typedef struct {
 #define ALN_CIGAR_D 2u
 
 /* Bytes of device workspace aln_align_batch needs for n_pairs pairs whose lengths are at most
- * max_n (queries) and max_m (subjects), for the given flags.  Returns ALN_OK and sets *bytes. */
+ * max_n (queries) and max_m (subjects) and sum to total_q / total_s letters, for the given flags.
+ * Returns ALN_OK and sets *bytes. */
 aln_status_t aln_batch_workspace_size(const aln_scoring_t* scoring, int64_t n_pairs, int64_t max_n,
-                                      int64_t max_m, uint32_t flags, size_t* bytes);
+                                      int64_t max_m, int64_t total_q, int64_t total_s, uint32_t flags,
+                                      size_t* bytes);
 
-/* Aligns n_pairs independent pairs (inter-sequence parallelism, Sec. VI; the batched form of the
- * recurrence above).
+/* Aligns n_pairs independent pairs.  Small pairs run one pair per lane (inter-sequence parallelism,
+ * Sec. VI); in score-only calls, pairs with n*m >= 2^20 run on the band wavefront of aln_align_long
+ * instead, all of them sharing one device-wide work queue (the dynamic wavefront of Sec. IV-A).  The
+ * routing is decided on the device, so the host needs no copy of the lengths.
  *   q, s          DEVICE  concatenated uint8 codes of all queries / subjects
  *   q_off, s_off  DEVICE  int64[n_pairs+1]; pair k is q[q_off[k]:q_off[k+1]] vs s[s_off[k]:s_off[k+1]]
  *   max_n, max_m  upper bounds of the lengths (pairs above them get ALN_RES_TOO_LONG)
+ *   total_q, total_s  q_off[n_pairs] and s_off[n_pairs] (upper bounds suffice)
  *   flags         ALN_SCORE_ONLY or ALN_TRACEBACK, optionally | ALN_FORCE_INT32 / ALN_FORCE_INT16
  *   out           DEVICE  aln_result_t[n_pairs]
  *   cigar         DEVICE  uint32 CIGAR words; pair k owns cigar[cigar_off[k]:cigar_off[k+1]]
@@ -121,9 +127,40 @@ aln_status_t aln_batch_workspace_size(const aln_scoring_t* scoring, int64_t n_pa
  *   workspace     DEVICE  at least aln_batch_workspace_size(...) bytes, 256-byte aligned
  * Ownership: the caller owns every buffer; nothing is retained after the call's work completes. */
 aln_status_t aln_align_batch(const aln_scoring_t* scoring, int64_t n_pairs, const uint8_t* q, const int64_t* q_off,
-                             const uint8_t* s, const int64_t* s_off, int64_t max_n, int64_t max_m, uint32_t flags,
-                             aln_result_t* out, uint32_t* cigar, const int64_t* cigar_off, void* workspace,
-                             size_t workspace_bytes, hipStream_t stream);
+                             const uint8_t* s, const int64_t* s_off, int64_t max_n, int64_t max_m, int64_t total_q,
+                             int64_t total_s, uint32_t flags, aln_result_t* out, uint32_t* cigar,
+                             const int64_t* cigar_off, void* workspace, size_t workspace_bytes, hipStream_t stream);
+
+/* Bytes of device workspace aln_align_long needs for an n x m problem. */
+aln_status_t aln_long_workspace_size(const aln_scoring_t* scoring, int64_t n, int64_t m, uint32_t flags,
+                                     size_t* bytes);
+
+/* Aligns one long pair with intra-sequence parallelism: the matrix is relaxed in bands of rows that
+ * move as a wavefront across the device (AnySeq Sec. IV-B tiles relaxed along anti-diagonals, each
+ * publishing its last row to the next).  Score and end cell only (q_begin = s_begin = -1).
+ *   q             DEVICE  n uint8 codes;  s  DEVICE  m uint8 codes
+ *   flags         ALN_SCORE_ONLY (ALN_TRACEBACK returns ALN_E_UNSUPPORTED)
+ *   out           DEVICE  one aln_result_t
+ *   workspace     DEVICE  at least aln_long_workspace_size(...) bytes, 256-byte aligned; it holds the
+ *                         bottom row of every band, (n / 256) * (m + 1) * 8 bytes.
+ * Exactness: 32-bit lanes; the call returns ALN_E_SCORING if the score range of an n x m problem
+ * could leave +-2^28. */
+aln_status_t aln_align_long(const aln_scoring_t* scoring, const uint8_t* q, int64_t n, const uint8_t* s, int64_t m,
+                            uint32_t flags, aln_result_t* out, void* workspace, size_t workspace_bytes,
+                            hipStream_t stream);
+
+/* Kernel timing, a profiling aid.  While enabled, every kernel the library enqueues is bracketed by
+ * HIP events recorded on the same stream; aln_profile_read waits for those events and returns, per
+ * kernel family, the number of launches and their summed device time since the last reset.  Not for
+ * use under graph capture (it records events).  Host-side only; returns ALN_OK or ALN_E_INVALID. */
+typedef struct {
+  char name[48];
+  int64_t launches;
+  double total_ms;
+} aln_profile_entry_t;
+aln_status_t aln_profile_enable(int on);
+aln_status_t aln_profile_reset(void);
+aln_status_t aln_profile_read(aln_profile_entry_t* entries, int32_t max_entries, int32_t* n_entries);
 
 /* Human-readable text of a status code (static storage). */
 const char* aln_status_string(aln_status_t status);

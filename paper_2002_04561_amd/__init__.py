@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libmialign.so")
 
 GLOBAL, LOCAL, SEMIGLOBAL = 0, 1, 2
 SCORE_ONLY, TRACEBACK, FORCE_INT32, FORCE_INT16 = 0, 1, 2, 4
-RES_INT32_REDO, RES_CIGAR_TRUNC, RES_BAD_CODE, RES_TOO_LONG = 1, 2, 4, 8
+RES_INT32_REDO, RES_CIGAR_TRUNC, RES_BAD_CODE, RES_TOO_LONG, RES_DEVICE_ERROR = 1, 2, 4, 8, 16
 CIGAR_M, CIGAR_I, CIGAR_D = 0, 1, 2
 
 STATUS = {0: "ALN_OK", -1: "ALN_E_INVALID", -2: "ALN_E_ALPHABET", -3: "ALN_E_SCORING", -4: "ALN_E_WORKSPACE",
@@ -46,11 +46,21 @@ _lib = None
 
 _SIGNATURES = {
     "aln_batch_workspace_size": (ctypes.c_int32, [ctypes.POINTER(aln_scoring_t), ctypes.c_int64, ctypes.c_int64,
-                                                  ctypes.c_int64, ctypes.c_uint32, ctypes.POINTER(ctypes.c_size_t)]),
+                                                  ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, ctypes.c_uint32,
+                                                  ctypes.POINTER(ctypes.c_size_t)]),
     "aln_align_batch": (ctypes.c_int32, [ctypes.POINTER(aln_scoring_t), ctypes.c_int64, ctypes.c_void_p,
                                          ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
-                                         ctypes.c_int64, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_void_p,
-                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
+                                         ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, ctypes.c_uint32,
+                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                         ctypes.c_size_t, ctypes.c_void_p]),
+    "aln_long_workspace_size": (ctypes.c_int32, [ctypes.POINTER(aln_scoring_t), ctypes.c_int64, ctypes.c_int64,
+                                                 ctypes.c_uint32, ctypes.POINTER(ctypes.c_size_t)]),
+    "aln_align_long": (ctypes.c_int32, [ctypes.POINTER(aln_scoring_t), ctypes.c_void_p, ctypes.c_int64,
+                                        ctypes.c_void_p, ctypes.c_int64, ctypes.c_uint32, ctypes.c_void_p,
+                                        ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
+    "aln_profile_enable": (ctypes.c_int32, [ctypes.c_int]),
+    "aln_profile_reset": (ctypes.c_int32, []),
+    "aln_profile_read": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
     "aln_status_string": (ctypes.c_char_p, [ctypes.c_int32]),
     "aln_version": (ctypes.c_char_p, []),
 }
@@ -111,22 +121,84 @@ def _stream_handle(stream) -> Optional[int]:
     return int(stream.cuda_stream)
 
 
-def aln_batch_workspace_size(scoring: Scoring, n_pairs: int, max_n: int, max_m: int, flags: int) -> int:
+def aln_batch_workspace_size(scoring: Scoring, n_pairs: int, max_n: int, max_m: int, total_q: int, total_s: int,
+                             flags: int) -> int:
     out = ctypes.c_size_t(0)
     sc = scoring.c()
-    st = lib().aln_batch_workspace_size(ctypes.byref(sc), n_pairs, max_n, max_m, flags, ctypes.byref(out))
+    st = lib().aln_batch_workspace_size(ctypes.byref(sc), n_pairs, max_n, max_m, total_q, total_s, flags,
+                                        ctypes.byref(out))
     if st != 0:
         raise AlnError(st, "aln_batch_workspace_size")
     return int(out.value)
 
 
-def aln_align_batch(scoring: Scoring, n_pairs: int, q, q_off, s, s_off, max_n: int, max_m: int, flags: int, out,
-                    cigar, cigar_off, workspace, workspace_bytes: int, stream=None) -> int:
+def aln_align_batch(scoring: Scoring, n_pairs: int, q, q_off, s, s_off, max_n: int, max_m: int, total_q: int,
+                    total_s: int, flags: int, out, cigar, cigar_off, workspace, workspace_bytes: int,
+                    stream=None) -> int:
     """Same arguments as the C function; tensors are torch device tensors.  Returns the status code."""
     sc = scoring.c()
     return int(lib().aln_align_batch(ctypes.byref(sc), n_pairs, _ptr(q), _ptr(q_off), _ptr(s), _ptr(s_off), max_n,
-                                     max_m, flags, _ptr(out), _ptr(cigar), _ptr(cigar_off), _ptr(workspace),
-                                     workspace_bytes, _stream_handle(stream)))
+                                     max_m, total_q, total_s, flags, _ptr(out), _ptr(cigar), _ptr(cigar_off),
+                                     _ptr(workspace), workspace_bytes, _stream_handle(stream)))
+
+
+def aln_long_workspace_size(scoring: Scoring, n: int, m: int, flags: int = SCORE_ONLY) -> int:
+    out = ctypes.c_size_t(0)
+    sc = scoring.c()
+    st = lib().aln_long_workspace_size(ctypes.byref(sc), n, m, flags, ctypes.byref(out))
+    if st != 0:
+        raise AlnError(st, "aln_long_workspace_size")
+    return int(out.value)
+
+
+def aln_align_long(scoring: Scoring, q, n: int, s, m: int, flags: int, out, workspace, workspace_bytes: int,
+                   stream=None) -> int:
+    sc = scoring.c()
+    return int(lib().aln_align_long(ctypes.byref(sc), _ptr(q), n, _ptr(s), m, flags, _ptr(out), _ptr(workspace),
+                                    workspace_bytes, _stream_handle(stream)))
+
+
+class LongAligner:
+    """Owns the result and workspace buffers for aln_align_long on one device-resident pair."""
+
+    def __init__(self, scoring: Scoring, q, s, flags: int = SCORE_ONLY, device="cuda"):
+        import torch
+        self.scoring, self.q, self.s, self.flags = scoring, q, s, flags
+        self.n, self.m = int(q.numel()), int(s.numel())
+        self.out = torch.empty(8, dtype=torch.int32, device=device)
+        self.ws_bytes = aln_long_workspace_size(scoring, self.n, self.m, flags)
+        self.workspace = torch.empty(max(self.ws_bytes, 256), dtype=torch.uint8, device=device)
+
+    def run(self, stream=None):
+        st = aln_align_long(self.scoring, self.q, self.n, self.s, self.m, self.flags, self.out, self.workspace,
+                            self.ws_bytes, stream)
+        if st != 0:
+            raise AlnError(st, "aln_align_long")
+
+    def result(self):
+        return self.out.to("cpu").numpy().view(RESULT_DTYPE)[0]
+
+
+class aln_profile_entry_t(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 48), ("launches", ctypes.c_int64), ("total_ms", ctypes.c_double)]
+
+
+def aln_profile_enable(on: bool) -> None:
+    lib().aln_profile_enable(1 if on else 0)
+
+
+def aln_profile_reset() -> None:
+    lib().aln_profile_reset()
+
+
+def aln_profile_read() -> dict:
+    """{kernel family: (launches, total_ms)} accumulated since the last reset (waits for the events)."""
+    arr = (aln_profile_entry_t * 64)()
+    n = ctypes.c_int32(0)
+    st = lib().aln_profile_read(ctypes.cast(arr, ctypes.c_void_p), 64, ctypes.byref(n))
+    if st != 0:
+        raise AlnError(st, "aln_profile_read")
+    return {arr[k].name.decode(): (int(arr[k].launches), float(arr[k].total_ms)) for k in range(min(n.value, 64))}
 
 
 def aln_status_string(status: int) -> str:
@@ -141,13 +213,15 @@ class BatchAligner:
     """Owns the device buffers for repeated aln_align_batch calls over one set of device-resident pairs."""
 
     def __init__(self, scoring: Scoring, q, q_off, s, s_off, max_n: int, max_m: int, flags: int = SCORE_ONLY,
-                 cigar_capacity=None, device="cuda"):
+                 cigar_capacity=None, device="cuda", total_q=None, total_s=None):
         import torch
         self.torch = torch
         self.scoring = scoring
         self.q, self.q_off, self.s, self.s_off = q, q_off, s, s_off
         self.n_pairs = int(q_off.numel()) - 1
         self.max_n, self.max_m, self.flags = int(max_n), int(max_m), int(flags)
+        self.total_q = int(q.numel()) if total_q is None else int(total_q)
+        self.total_s = int(s.numel()) if total_s is None else int(total_s)
         self.out = torch.empty(self.n_pairs * 8, dtype=torch.int32, device=device)
         self.cigar = self.cigar_off = None
         if flags & TRACEBACK:
@@ -162,23 +236,33 @@ class BatchAligner:
             np.cumsum(cap, out=coff[1:])
             self.cigar_off = torch.from_numpy(coff).to(device)
             self.cigar = torch.empty(max(int(coff[-1]), 1), dtype=torch.int32, device=device)
-        self.ws_bytes = aln_batch_workspace_size(scoring, self.n_pairs, self.max_n, self.max_m, self.flags)
+        self.ws_bytes = aln_batch_workspace_size(scoring, self.n_pairs, self.max_n, self.max_m, self.total_q,
+                                                 self.total_s, self.flags)
         self.workspace = torch.empty(max(self.ws_bytes, 256), dtype=torch.uint8, device=device)
 
     def run(self, stream=None):
         st = aln_align_batch(self.scoring, self.n_pairs, self.q, self.q_off, self.s, self.s_off, self.max_n,
-                             self.max_m, self.flags, self.out, self.cigar, self.cigar_off, self.workspace,
-                             self.ws_bytes, stream)
+                             self.max_m, self.total_q, self.total_s, self.flags, self.out, self.cigar,
+                             self.cigar_off, self.workspace, self.ws_bytes, stream)
         if st != 0:
             raise AlnError(st, "aln_align_batch")
 
     def results(self) -> np.ndarray:
         return self.out.to("cpu").numpy().view(RESULT_DTYPE)
 
-    def cigars(self):
+    def cigars(self, idx=None):
+        """CIGAR run lists [(length, op), ...] of all pairs, or of the pairs in idx (dict k -> runs)."""
         res = self.results()
         cig = self.cigar.to("cpu").numpy().view(np.uint32)
         coff = self.cigar_off.to("cpu").numpy()
+        if idx is not None:
+            got = {}
+            for k in idx:
+                k = int(k)
+                L = int(res["cigar_len"][k])
+                w = cig[coff[k]:coff[k] + min(L, coff[k + 1] - coff[k])]
+                got[k] = [(int(x) >> 4, int(x) & 15) for x in w]
+            return got
         out = []
         for k in range(self.n_pairs):
             L = int(res["cigar_len"][k])

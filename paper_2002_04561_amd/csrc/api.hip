@@ -92,25 +92,70 @@ const char* aln_status_string(aln_status_t st) {
   }
 }
 
+__global__ void fill_i32_kernel(int* p, int n, int v) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) p[k] = v;
+}
+
+// Workspace of a batch call:
+//   [slabs: shared by the 16-bit kernel and the 32-bit kernel, which run one after the other]
+//   [redo list: n_pairs ints + counter]
+//   [split plan + wavefront engine (score-only calls)]
+struct BatchLayout {
+  BatchPlan bp;
+  BatchPlan16 bp16;
+  SplitPlan sp;
+  bool use16;
+  size_t off_redo, off_redo_cnt, off_split, total;
+};
+
+static aln_status_t batch_layout(const KParams& kp, int64_t n_pairs, int64_t max_n, int64_t max_m, int64_t total_q,
+                                 int64_t total_s, uint32_t flags, BatchLayout* L) {
+  const bool tb = (flags & ALN_TRACEBACK) != 0;
+  aln_status_t st = plan_batch_i32(kp, n_pairs, max_n, max_m, tb, &L->bp);
+  if (st != ALN_OK) return st;
+  L->use16 = !(flags & ALN_FORCE_INT32) && max_m < 32767;
+  size_t slabs = L->bp.total_bytes;
+  if (L->use16) {
+    st = plan_batch_i16(kp, n_pairs, max_n, max_m, tb, &L->bp16);
+    if (st != ALN_OK) return st;
+    if (L->bp16.total_bytes > slabs) slabs = L->bp16.total_bytes;
+  }
+  size_t off = (slabs + 255) & ~(size_t)255;
+  L->off_redo = off;
+  off += ((size_t)(n_pairs + 1) * sizeof(int) + 255) & ~(size_t)255;
+  L->off_redo_cnt = off;
+  off += 256;
+  L->off_split = off;
+  if (!tb) {
+    st = plan_split(n_pairs, total_q, total_s, &L->sp);
+    if (st != ALN_OK) return st;
+    off += L->sp.total_bytes;
+  }
+  L->total = off;
+  return ALN_OK;
+}
+
 aln_status_t aln_batch_workspace_size(const aln_scoring_t* scoring, int64_t n_pairs, int64_t max_n, int64_t max_m,
-                                      uint32_t flags, size_t* bytes) {
-  if (!bytes || n_pairs < 0 || max_n < 0 || max_m < 0) return ALN_E_INVALID;
+                                      int64_t total_q, int64_t total_s, uint32_t flags, size_t* bytes) {
+  if (!bytes || n_pairs < 0 || max_n < 0 || max_m < 0 || total_q < 0 || total_s < 0) return ALN_E_INVALID;
+  if (flags & ~(ALN_TRACEBACK | ALN_FORCE_INT32 | ALN_FORCE_INT16)) return ALN_E_INVALID;
   KParams kp;
   aln_status_t st = make_params(scoring, &kp);
   if (st != ALN_OK) return st;
   if (!fits_i32(kp, max_n, max_m)) return ALN_E_SCORING;
-  BatchPlan pl;
-  st = plan_batch_i32(kp, n_pairs, max_n, max_m, (flags & ALN_TRACEBACK) != 0, &pl);
+  BatchLayout L;
+  st = batch_layout(kp, n_pairs, max_n, max_m, total_q, total_s, flags, &L);
   if (st != ALN_OK) return st;
-  *bytes = pl.total_bytes;
+  *bytes = L.total;
   return ALN_OK;
 }
 
 aln_status_t aln_align_batch(const aln_scoring_t* scoring, int64_t n_pairs, const uint8_t* q, const int64_t* q_off,
-                             const uint8_t* s, const int64_t* s_off, int64_t max_n, int64_t max_m, uint32_t flags,
-                             aln_result_t* out, uint32_t* cigar, const int64_t* cigar_off, void* workspace,
-                             size_t workspace_bytes, hipStream_t stream) {
-  if (n_pairs < 0 || max_n < 0 || max_m < 0) return ALN_E_INVALID;
+                             const uint8_t* s, const int64_t* s_off, int64_t max_n, int64_t max_m, int64_t total_q,
+                             int64_t total_s, uint32_t flags, aln_result_t* out, uint32_t* cigar,
+                             const int64_t* cigar_off, void* workspace, size_t workspace_bytes, hipStream_t stream) {
+  if (n_pairs < 0 || max_n < 0 || max_m < 0 || total_q < 0 || total_s < 0) return ALN_E_INVALID;
   if (flags & ~(ALN_TRACEBACK | ALN_FORCE_INT32 | ALN_FORCE_INT16)) return ALN_E_INVALID;
   KParams kp;
   aln_status_t st = make_params(scoring, &kp);
@@ -118,14 +163,87 @@ aln_status_t aln_align_batch(const aln_scoring_t* scoring, int64_t n_pairs, cons
   if (n_pairs == 0) return ALN_OK;
   if (!q_off || !s_off || !out) return ALN_E_INVALID;
   if ((!q && max_n > 0) || (!s && max_m > 0)) return ALN_E_INVALID;
+  if (n_pairs >= (1ll << 31)) return ALN_E_INVALID;
   const bool tb = (flags & ALN_TRACEBACK) != 0;
   if (tb && (!cigar || !cigar_off)) return ALN_E_INVALID;
   if (!fits_i32(kp, max_n, max_m)) return ALN_E_SCORING;
-  BatchPlan pl;
-  st = plan_batch_i32(kp, n_pairs, max_n, max_m, tb, &pl);
+  BatchLayout L;
+  st = batch_layout(kp, n_pairs, max_n, max_m, total_q, total_s, flags, &L);
   if (st != ALN_OK) return st;
-  if (pl.total_bytes > 0 && (!workspace || workspace_bytes < pl.total_bytes)) return ALN_E_WORKSPACE;
-  return launch_batch_i32(kp, pl, q, q_off, s, s_off, tb, out, cigar, cigar_off, workspace, stream);
+  if (!workspace || workspace_bytes < L.total) return ALN_E_WORKSPACE;
+  char* base = static_cast<char*>(workspace);
+  int* redo_idx = reinterpret_cast<int*>(base + L.off_redo);
+  int* redo_cnt = reinterpret_cast<int*>(base + L.off_redo_cnt);
+
+  // which pairs the inter-sequence kernels see: all of them, or the small ones of a score-only call
+  const int* list = nullptr;
+  const int* list_cnt = nullptr;
+  if (!tb) {
+    char* split_ws = base + L.off_split;
+    launch_split(L.sp, n_pairs, q_off, s_off, max_n, max_m, split_ws, stream);
+    WfWs W = wf_view(split_ws + L.sp.wf_base, L.sp.wf);
+    st = launch_wf_i32(kp, W, q, s, out, L.sp.wf_waves, stream);
+    if (st != ALN_OK) return st;
+    list = reinterpret_cast<const int*>(split_ws + L.sp.off_small_idx);
+    list_cnt = reinterpret_cast<const int*>(split_ws + L.sp.off_small_cnt);
+  }
+  if (!L.use16)
+    return launch_batch_i32(kp, L.bp, q, q_off, s, s_off, tb, out, cigar, cigar_off, workspace, list, list_cnt, 0u,
+                            stream);
+  hipLaunchKernelGGL(fill_i32_kernel, dim3(1), dim3(64), 0, stream, redo_cnt, 1, 0);
+  I16Args a;
+  a.q = q;
+  a.q_off = q_off;
+  a.s = s;
+  a.s_off = s_off;
+  a.out = out;
+  a.cigar = cigar;
+  a.cigar_off = cigar_off;
+  a.ws = workspace;
+  a.idx = list;
+  a.idx_count = list_cnt;
+  a.redo_idx = redo_idx;
+  a.redo_cnt = redo_cnt;
+  a.force16 = (flags & ALN_FORCE_INT16) ? 1 : 0;
+  st = launch_batch_i16(kp, L.bp16, a, tb, stream);
+  if (st != ALN_OK) return st;
+  // pairs whose 16-bit range was not provably exact, or that saturated, are recomputed in 32 bits
+  return launch_batch_i32(kp, L.bp, q, q_off, s, s_off, tb, out, cigar, cigar_off, workspace, redo_idx, redo_cnt,
+                          ALN_RES_INT32_REDO, stream);
+}
+
+aln_status_t aln_long_workspace_size(const aln_scoring_t* scoring, int64_t n, int64_t m, uint32_t flags,
+                                     size_t* bytes) {
+  if (!bytes || n < 0 || m < 0 || n >= (1ll << 31) || m >= (1ll << 31)) return ALN_E_INVALID;
+  if (flags & ~(ALN_TRACEBACK | ALN_FORCE_INT32 | ALN_FORCE_INT16)) return ALN_E_INVALID;
+  if (flags & ALN_TRACEBACK) return ALN_E_UNSUPPORTED;
+  KParams kp;
+  aln_status_t st = make_params(scoring, &kp);
+  if (st != ALN_OK) return st;
+  if (!fits_i32(kp, n, m)) return ALN_E_SCORING;
+  LongPlan pl;
+  st = plan_long(n, m, &pl);
+  if (st != ALN_OK) return st;
+  *bytes = pl.total_bytes;
+  return ALN_OK;
+}
+
+aln_status_t aln_align_long(const aln_scoring_t* scoring, const uint8_t* q, int64_t n, const uint8_t* s, int64_t m,
+                            uint32_t flags, aln_result_t* out, void* workspace, size_t workspace_bytes,
+                            hipStream_t stream) {
+  if (n < 0 || m < 0 || n >= (1ll << 31) || m >= (1ll << 31) || !out) return ALN_E_INVALID;
+  if ((n > 0 && !q) || (m > 0 && !s)) return ALN_E_INVALID;
+  if (flags & ~(ALN_TRACEBACK | ALN_FORCE_INT32 | ALN_FORCE_INT16)) return ALN_E_INVALID;
+  if (flags & ALN_TRACEBACK) return ALN_E_UNSUPPORTED;
+  KParams kp;
+  aln_status_t st = make_params(scoring, &kp);
+  if (st != ALN_OK) return st;
+  if (!fits_i32(kp, n, m)) return ALN_E_SCORING;
+  LongPlan pl;
+  st = plan_long(n, m, &pl);
+  if (st != ALN_OK) return st;
+  if (!workspace || workspace_bytes < pl.total_bytes) return ALN_E_WORKSPACE;
+  return launch_long(kp, pl, q, n, s, m, out, workspace, stream);
 }
 
 }  // extern "C"

@@ -1,0 +1,454 @@
+// Inter-sequence batch kernel, packed 16-bit lanes: two pairs per lane.
+//
+// Lane l of a wave carries pair slot l in the low halves and slot 64+l in the
+// high halves of every register, so one v_pk_* instruction relaxes a cell of
+// two independent pairs (the inter-task vectorisation of AnySeq Sec. IV-A with
+// 16-bit scores, Sec. V).  Each lane walks its two matrices in strips of R
+// query rows.  The substitution scores of a strip come from a query profile in
+// LDS -- for every letter c, the R scores sigma(q_i, c) as int16 -- so one
+// 16-byte LDS read per pair and column delivers eight rows, and one v_perm
+// merges the two pairs' scores of a row.
+//
+// All arithmetic saturates, so -infinity is -32768 and never wraps.  Exactness:
+// global and semi-global pairs run here only when their score range provably
+// fits (every value lies in [3*go + (n+m)*ge, min(n,m)*max(sigma_max,0)],
+// the 16-bit bound of Sec. IV-A made explicit); local pairs also run when the
+// bound fails, and a pair whose best score reached 32767 may have saturated.
+// Both kinds go to a redo list that the 32-bit kernel recomputes exactly.
+#include "internal.h"
+#include "walk.h"
+
+namespace mialign {
+namespace {
+
+typedef short s2 __attribute__((ext_vector_type(2)));
+typedef unsigned short u2 __attribute__((ext_vector_type(2)));
+
+constexpr int kI16WavesPerBlock = 2;
+constexpr int kI16Block = 64 * kI16WavesPerBlock;
+constexpr int kI16WavesPerCU = 8;
+constexpr int kPadSigma16 = -16384;
+constexpr int kBound16 = 32000;
+
+__device__ __forceinline__ s2 adds(s2 a, s2 b) { return __builtin_elementwise_add_sat(a, b); }
+__device__ __forceinline__ s2 subs(s2 a, s2 b) { return __builtin_elementwise_sub_sat(a, b); }
+__device__ __forceinline__ s2 mx(s2 a, s2 b) { return __builtin_elementwise_max(a, b); }
+__device__ __forceinline__ s2 mn(s2 a, s2 b) { return __builtin_elementwise_min(a, b); }
+__device__ __forceinline__ s2 sp(int v) {
+  s2 r = {(short)v, (short)v};
+  return r;
+}
+__device__ __forceinline__ s2 pk(int lo, int hi) {
+  s2 r = {(short)lo, (short)hi};
+  return r;
+}
+__device__ __forceinline__ uint32_t bits(s2 x) { return __builtin_bit_cast(uint32_t, x); }
+__device__ __forceinline__ s2 from_bits(uint32_t x) { return __builtin_bit_cast(s2, x); }
+__device__ __forceinline__ int lo16(s2 x) { return (int)x.x; }
+__device__ __forceinline__ int hi16(s2 x) { return (int)x.y; }
+// a * b + c on unsigned halves (small non-negative values)
+__device__ __forceinline__ s2 mad_u(s2 a, s2 b, s2 c) {
+  const u2 r = __builtin_bit_cast(u2, a) * __builtin_bit_cast(u2, b) + __builtin_bit_cast(u2, c);
+  return __builtin_bit_cast(s2, r);
+}
+
+__device__ __forceinline__ bool fits16(const KParams& P, int n, int m) {
+  const int mn = n < m ? n : m;
+  const long long up = (long long)mn * (P.sigma_max > 0 ? P.sigma_max : 0);
+  const long long lo = 3ll * P.go + (long long)(n + m) * P.ge;
+  return up <= kBound16 && lo >= -kBound16 && m < 32767;
+}
+
+template <int MODE, bool AFFINE, bool TB, int R>
+__global__ __launch_bounds__(kI16Block) void batch_i16_kernel(
+    const KParams P, const uint8_t* __restrict__ q, const int64_t* __restrict__ q_off, const uint8_t* __restrict__ s,
+    const int64_t* __restrict__ s_off, int64_t n_pairs, int64_t max_n, int64_t max_m, aln_result_t* __restrict__ out,
+    uint32_t* __restrict__ cigar, const int64_t* __restrict__ cigar_off, char* __restrict__ ws, size_t slab_bytes,
+    size_t rowbuf_bytes, const int* __restrict__ idx, const int* __restrict__ idx_count, int* __restrict__ redo_idx,
+    int* __restrict__ redo_cnt, int force16) {
+  static_assert(R % 8 == 0 || R == 4, "R must be 4 or a multiple of 8");
+  extern __shared__ char smem[];
+  int32_t* tab = reinterpret_cast<int32_t*>(smem);
+  for (int k = threadIdx.x; k < kTab * kTab; k += blockDim.x) {
+    const int a = k / kTab, b = k % kTab;
+    int32_t v;
+    if (a >= P.alphabet || b >= P.alphabet)
+      v = kPadSigma16;
+    else
+      v = P.use_table ? (int32_t)P.sig[a * kMaxAlphabet + b] : (a == b ? P.match : P.mismatch);
+    tab[k] = v;
+  }
+  __syncthreads();
+  const int AP = P.alphabet + 1;  // profile letters: the alphabet and the pad
+  const int lane = threadIdx.x & 63;
+  const int wib = threadIdx.x >> 6;
+  short* __restrict__ prof = reinterpret_cast<short*>(smem + kTab * kTab * 4) + (size_t)wib * 128 * AP * R;
+  short* __restrict__ profA = prof + (size_t)lane * AP * R;
+  short* __restrict__ profB = prof + (size_t)(64 + lane) * AP * R;
+
+  const int64_t wave = (int64_t)blockIdx.x * kI16WavesPerBlock + wib;
+  const int64_t n_waves = (int64_t)gridDim.x * kI16WavesPerBlock;
+  char* slab = ws + wave * slab_bytes;
+  uint2* __restrict__ rowbuf = reinterpret_cast<uint2*>(slab);
+  uint32_t* __restrict__ dirs = reinterpret_cast<uint32_t*>(slab + rowbuf_bytes);
+  constexpr int RW = (R + 3) / 4;  // direction words per column (4 rows x 2 pairs per word)
+  const int64_t count = idx ? (int64_t)*idx_count : n_pairs;
+  const int64_t groups = (count + 127) / 128;
+  const s2 ge2 = sp(P.ge), goe2 = sp(P.goe), go2 = sp(P.go), one = sp(1), zero = sp(0);
+  const s2 neg2 = sp(-32768);
+
+  for (int64_t g = wave; g < groups; g += n_waves) {
+    int64_t pp[2];
+    int nn[2], mm[2];
+    bool act[2], ok16[2], bad[2];
+    int64_t qb[2], sb[2];
+    uint32_t flg[2];
+    for (int h = 0; h < 2; ++h) {
+      const int64_t slot = g * 128 + h * 64 + lane;
+      act[h] = slot < count;
+      pp[h] = act[h] ? (idx ? (int64_t)idx[slot] : slot) : 0;
+      nn[h] = 0;
+      mm[h] = 0;
+      qb[h] = 0;
+      sb[h] = 0;
+      flg[h] = 0;
+      bad[h] = false;
+      ok16[h] = true;
+      if (act[h]) {
+        qb[h] = q_off[pp[h]];
+        sb[h] = s_off[pp[h]];
+        const int64_t a = q_off[pp[h] + 1] - qb[h], b = s_off[pp[h] + 1] - sb[h];
+        if (a > max_n || b > max_m || a < 0 || b < 0) {
+          flg[h] = ALN_RES_TOO_LONG;
+        } else {
+          nn[h] = (int)a;
+          mm[h] = (int)b;
+          const bool f = fits16(P, nn[h], mm[h]);
+          ok16[h] = f || (MODE == ALN_LOCAL && force16 && mm[h] < 32767);
+        }
+      }
+    }
+    const int nmax = wave_max_i32(max(nn[0], nn[1])), mmax = wave_max_i32(max(mm[0], mm[1]));
+    const int strips = (nmax + R - 1) / R;
+
+    // optimum bookkeeping per pair (scalars)
+    int best[2] = {0, 0}, bi[2] = {0, 0}, bj[2] = {0, 0};
+    if (MODE == ALN_SEMIGLOBAL) {
+      bj[0] = mm[0];
+      bj[1] = mm[1];
+    }
+    int brow[2] = {0, 0}, browj[2] = {0, 0}, hfin[2] = {0, 0};
+
+    for (int k = 0; k < strips; ++k) {
+      const int i0 = k * R;
+      // query profile of this strip for both pairs: prof[c*R + r] = sigma(q_{i0+r+1}, c)
+      for (int h = 0; h < 2; ++h) {
+        short* pr = h ? profB : profA;
+        int qc[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const int i = i0 + 1 + r;
+          int c = kPad;
+          if (i <= nn[h]) {
+            c = q[qb[h] + i - 1];
+            if (c >= P.alphabet) {
+              bad[h] = true;
+              c = kPad;
+            }
+          }
+          qc[r] = c * kTab;
+        }
+        for (int c = 0; c < AP; ++c) {
+          const int cc = c < P.alphabet ? c : kPad;
+          uint32_t w[R / 2 > 0 ? R / 2 : 1];
+#pragma unroll
+          for (int r = 0; r < R; r += 2)
+            w[r / 2] = (uint32_t)(tab[qc[r] + cc] & 0xffff) | ((uint32_t)tab[qc[r + 1] + cc] << 16);
+          uint32_t* dst = reinterpret_cast<uint32_t*>(pr + c * R);
+#pragma unroll
+          for (int r = 0; r < R / 2; ++r) dst[r] = w[r];
+        }
+      }
+      s2 hl[R], f[R], bv[R], bjr[R], cap[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int i = i0 + 1 + r;
+        hl[r] = sp((MODE == ALN_GLOBAL) ? P.go + i * P.ge : 0);
+        f[r] = neg2;
+        bv[r] = sp(-32768);
+        bjr[r] = zero;
+        cap[r] = zero;
+      }
+      s2 hdiag = sp((MODE == ALN_GLOBAL && i0 > 0) ? P.go + i0 * P.ge : 0);
+      const int rnA = nn[0] - 1 - i0, rnB = nn[1] - 1 - i0;
+      const bool lastA = rnA >= 0 && rnA < R, lastB = rnB >= 0 && rnB < R;
+      const bool track_last = (MODE == ALN_SEMIGLOBAL) && __any(lastA || lastB);
+      for (int j = 1; j <= mmax; ++j) {
+        int ca = P.alphabet, cb = P.alphabet;  // pad letter of the profile
+        if (j <= mm[0]) {
+          const int c = s[sb[0] + j - 1];
+          if (c < P.alphabet)
+            ca = c;
+          else
+            bad[0] = true;
+        }
+        if (j <= mm[1]) {
+          const int c = s[sb[1] + j - 1];
+          if (c < P.alphabet)
+            cb = c;
+          else
+            bad[1] = true;
+        }
+        s2 hup, eup;
+        if (k == 0) {
+          hup = sp((MODE == ALN_GLOBAL) ? P.go + j * P.ge : 0);
+          eup = neg2;
+        } else {
+          const uint2 v = rowbuf[(size_t)j * 64 + lane];
+          hup = from_bits(v.x);
+          eup = from_bits(v.y);
+        }
+        s2 hd = hdiag;
+        hdiag = hup;
+        const uint32_t* pa = reinterpret_cast<const uint32_t*>(profA + ca * R);
+        const uint32_t* pb = reinterpret_cast<const uint32_t*>(profB + cb * R);
+        uint32_t wa[R / 2], wb[R / 2];
+#pragma unroll
+        for (int r = 0; r < R / 2; ++r) {
+          wa[r] = pa[r];
+          wb[r] = pb[r];
+        }
+        uint32_t acc[RW];
+#pragma unroll
+        for (int w = 0; w < RW; ++w) acc[w] = 0;
+        const s2 jj = sp(j);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const s2 sg = from_bits(__builtin_amdgcn_perm(wb[r / 2], wa[r / 2], (r & 1) ? 0x07060302u : 0x05040100u));
+          const s2 hlo = hl[r];
+          const s2 d = adds(hd, sg);
+          const s2 tup = adds(hup, goe2);
+          const s2 e = AFFINE ? mx(adds(eup, ge2), tup) : adds(hup, ge2);
+          const s2 tle = adds(hlo, goe2);
+          const s2 ff = AFFINE ? mx(adds(f[r], ge2), tle) : adds(hlo, ge2);
+          s2 hv = mx(mx(d, e), ff);
+          if (MODE == ALN_LOCAL) hv = mx(hv, zero);
+          if (TB) {
+            const s2 bd = mn(subs(hv, d), one);
+            const s2 be = mn(subs(hv, e), one);
+            s2 hs = mad_u(bd, be, bd);
+            if (MODE == ALN_LOCAL) hs = mx(hs, mad_u(subs(one, mn(hv, one)), sp(3), zero));
+            s2 nib = hs;
+            if (AFFINE) {
+              nib = mad_u(mn(subs(e, tup), one), sp(4), nib);
+              nib = mad_u(mn(subs(ff, tle), one), sp(8), nib);
+            }
+            acc[r / 4] |= bits(nib) << (4 * (r & 3));
+          }
+          if (MODE == ALN_LOCAL) {
+            const s2 gt = mn(mx(subs(hv, bv[r]), zero), one);
+            bjr[r] = mad_u(gt, subs(jj, bjr[r]), bjr[r]);
+            bv[r] = mx(bv[r], hv);
+          }
+          f[r] = ff;
+          hl[r] = hv;
+          hd = hlo;
+          hup = hv;
+          eup = e;
+        }
+        if (MODE != ALN_LOCAL && (j == mm[0] || j == mm[1])) {
+          const uint32_t msk = (j == mm[0] ? 0x0000ffffu : 0u) | (j == mm[1] ? 0xffff0000u : 0u);
+#pragma unroll
+          for (int r = 0; r < R; ++r) cap[r] = from_bits((bits(cap[r]) & ~msk) | (bits(hl[r]) & msk));
+        }
+        if (track_last) {
+          int va = 0, vb = 0;
+#pragma unroll
+          for (int r = 0; r < R; ++r) {
+            if (r == rnA) va = lo16(hl[r]);
+            if (r == rnB) vb = hi16(hl[r]);
+          }
+          if (lastA && j <= mm[0] && va > brow[0]) {
+            brow[0] = va;
+            browj[0] = j;
+          }
+          if (lastB && j <= mm[1] && vb > brow[1]) {
+            brow[1] = vb;
+            browj[1] = j;
+          }
+        }
+        if (k + 1 < strips) rowbuf[(size_t)j * 64 + lane] = make_uint2(bits(hup), bits(eup));
+        if (TB) {
+#pragma unroll
+          for (int w = 0; w < RW; ++w)
+            dirs[(((size_t)k * RW + w) * (size_t)max_m + (size_t)(j - 1)) * 64 + lane] = acc[w];
+        }
+      }
+      // merge this strip's rows in row order
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int i = i0 + 1 + r;
+        for (int h = 0; h < 2; ++h) {
+          if (MODE == ALN_LOCAL) {
+            const int v = h ? hi16(bv[r]) : lo16(bv[r]);
+            if (i <= nn[h] && v > best[h]) {
+              best[h] = v;
+              bi[h] = i;
+              bj[h] = h ? hi16(bjr[r]) : lo16(bjr[r]);
+            }
+          } else {
+            const int v = h ? hi16(cap[r]) : lo16(cap[r]);
+            if (MODE == ALN_SEMIGLOBAL && i < nn[h] && v > best[h]) {
+              best[h] = v;
+              bi[h] = i;
+              bj[h] = mm[h];
+            }
+            if (MODE == ALN_GLOBAL && i == nn[h]) hfin[h] = v;
+          }
+        }
+      }
+    }
+
+    for (int h = 0; h < 2; ++h) {
+      if (!act[h]) continue;
+      const int n = nn[h], m = mm[h];
+      int sc = best[h], ei = bi[h], ej = bj[h];
+      if (MODE == ALN_SEMIGLOBAL) {
+        if (n == 0 || m == 0) {
+          sc = 0;
+          ei = 0;
+          ej = 0;
+        } else if (brow[h] > sc) {
+          sc = brow[h];
+          ei = n;
+          ej = browj[h];
+        }
+      } else if (MODE == ALN_GLOBAL) {
+        ei = n;
+        ej = m;
+        sc = (n == 0 || m == 0) ? ((n + m > 0) ? P.go + (n + m) * P.ge : 0) : hfin[h];
+      }
+      const bool saturated = (MODE == ALN_LOCAL) && sc >= 32767;
+      if (!flg[h] && !bad[h] && (!ok16[h] || saturated)) {
+        const int k = atomicAdd(redo_cnt, 1);
+        redo_idx[k] = (int)pp[h];
+        continue;  // the 32-bit kernel writes this pair's result
+      }
+      aln_result_t res;
+      res.score = sc;
+      res.q_begin = -1;
+      res.q_end = ei;
+      res.s_begin = -1;
+      res.s_end = ej;
+      res.cigar_len = 0;
+      res.reserved = 0;
+      uint32_t fl = flg[h];
+      if (bad[h]) fl |= ALN_RES_BAD_CODE;
+      if (fl) {
+        res.score = 0;
+        res.q_end = 0;
+        res.s_end = 0;
+      } else if (TB) {
+        const int64_t c0 = cigar_off[pp[h]];
+        const int64_t capw = cigar_off[pp[h] + 1] - c0;
+        const int shift = 16 * h;
+        auto code = [&](int ii, int jx) -> uint32_t {
+          const int kk = (ii - 1) / R, rr = (ii - 1) % R;
+          const uint32_t w = dirs[(((size_t)kk * RW + rr / 4) * (size_t)max_m + (size_t)(jx - 1)) * 64 + lane];
+          return (w >> (shift + 4 * (rr & 3))) & 15u;
+        };
+        int qbeg, sbeg, runs;
+        walk_back<MODE>(code, ei, ej, cigar + c0, capw, &qbeg, &sbeg, &runs);
+        res.q_begin = qbeg;
+        res.s_begin = sbeg;
+        res.cigar_len = runs;
+        if (runs > capw) fl |= ALN_RES_CIGAR_TRUNC;
+      }
+      res.flags = fl;
+      out[pp[h]] = res;
+    }
+  }
+}
+
+template <int MODE, bool AFFINE, bool TB, int R>
+void launch_i16_t(const KParams& kp, const BatchPlan16& pl, const I16Args& a, hipStream_t stream) {
+  const int blocks = (pl.n_waves + kI16WavesPerBlock - 1) / kI16WavesPerBlock;
+  const size_t lds = (size_t)kTab * kTab * 4 + (size_t)kI16WavesPerBlock * 128 * (kp.alphabet + 1) * R * 2;
+  ProfScope prof(TB ? "batch_i16_traceback" : "batch_i16_score", stream);
+  hipLaunchKernelGGL((batch_i16_kernel<MODE, AFFINE, TB, R>), dim3(blocks), dim3(kI16Block), lds, stream, kp, a.q,
+                     a.q_off, a.s, a.s_off, pl.n_pairs, pl.max_n, pl.max_m, a.out, a.cigar, a.cigar_off,
+                     static_cast<char*>(a.ws), pl.slab_bytes, pl.rowbuf_bytes, a.idx, a.idx_count, a.redo_idx,
+                     a.redo_cnt, a.force16);
+}
+
+template <int MODE, bool AFFINE, bool TB>
+void launch_i16_r(const KParams& kp, const BatchPlan16& pl, const I16Args& a, hipStream_t st) {
+  if (pl.R == 16)
+    launch_i16_t<MODE, AFFINE, TB, 16>(kp, pl, a, st);
+  else if (pl.R == 8)
+    launch_i16_t<MODE, AFFINE, TB, 8>(kp, pl, a, st);
+  else
+    launch_i16_t<MODE, AFFINE, TB, 4>(kp, pl, a, st);
+}
+
+template <int MODE>
+void launch_i16_m(const KParams& kp, const BatchPlan16& pl, const I16Args& a, bool tb, hipStream_t st) {
+  const bool affine = kp.go != 0;
+  if (affine) {
+    if (tb)
+      launch_i16_r<MODE, true, true>(kp, pl, a, st);
+    else
+      launch_i16_r<MODE, true, false>(kp, pl, a, st);
+  } else {
+    if (tb)
+      launch_i16_r<MODE, false, true>(kp, pl, a, st);
+    else
+      launch_i16_r<MODE, false, false>(kp, pl, a, st);
+  }
+}
+
+size_t round256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+}  // namespace
+
+aln_status_t plan_batch_i16(const KParams& kp, int64_t n_pairs, int64_t max_n, int64_t max_m, bool tb,
+                            BatchPlan16* pl) {
+  pl->n_pairs = n_pairs;
+  pl->max_n = max_n;
+  pl->max_m = max_m;
+  // rows per strip: the LDS query profile holds 128 pairs x (alphabet+1) letters x R rows per wave
+  pl->R = kp.alphabet <= 4 ? 16 : (kp.alphabet <= 12 ? 8 : 4);
+  const int64_t strips = (max_n + pl->R - 1) / pl->R;
+  const int RW = (pl->R + 3) / 4;
+  const int64_t groups = (n_pairs + 127) / 128;
+  const int cus = device_cu_count();
+  if (cus <= 0) return ALN_E_DEVICE;
+  int64_t waves = (int64_t)cus * kI16WavesPerCU;
+  if (groups < waves) waves = groups;
+  if (waves < 1) waves = 1;
+  waves = (waves + kI16WavesPerBlock - 1) / kI16WavesPerBlock * kI16WavesPerBlock;
+  pl->n_waves = (int)waves;
+  pl->rowbuf_bytes = round256((size_t)(max_m + 1) * 64 * sizeof(uint2));
+  pl->slab_bytes = pl->rowbuf_bytes + (tb ? round256((size_t)strips * RW * (size_t)max_m * 64 * 4) : 0);
+  pl->total_bytes = (size_t)pl->n_waves * pl->slab_bytes;
+  return ALN_OK;
+}
+
+aln_status_t launch_batch_i16(const KParams& kp, const BatchPlan16& pl, const I16Args& a, bool tb,
+                              hipStream_t stream) {
+  if (pl.n_pairs == 0) return ALN_OK;
+  switch (kp.mode) {
+    case ALN_GLOBAL:
+      launch_i16_m<ALN_GLOBAL>(kp, pl, a, tb, stream);
+      break;
+    case ALN_LOCAL:
+      launch_i16_m<ALN_LOCAL>(kp, pl, a, tb, stream);
+      break;
+    default:
+      launch_i16_m<ALN_SEMIGLOBAL>(kp, pl, a, tb, stream);
+      break;
+  }
+  return hipGetLastError() == hipSuccess ? ALN_OK : ALN_E_DEVICE;
+}
+
+}  // namespace mialign

@@ -8,13 +8,13 @@
 // relaxation of AnySeq Sec. III-A (a strip needs its top row computed before
 // and publishes its last row) applied per lane.
 //
-// With traceback, every cell also records a 4-bit predecessor code (the
-// NextStep.predc of Sec. III-B extended by the two gap-open bits of the affine
-// model): bits 0-1 = source of H (0 diagonal, 1 E, 2 F, 3 local zero),
-// bit 2 = E(i,j) opened from H(i-1,j), bit 3 = F(i,j) opened from H(i,j-1).
+// With traceback, every cell also records the 4-bit predecessor code of
+// walk.h (the NextStep.predc of Sec. III-B plus the two gap-extension bits of
+// the affine model).
 // The R codes of one column of a strip form one 32-bit word.  The same wave
 // then walks each pair back from its optimum and writes the CIGAR.
 #include "internal.h"
+#include "walk.h"
 
 namespace mialign {
 namespace {
@@ -24,94 +24,12 @@ constexpr int kWavesPerBlock = 4;
 constexpr int kBlock = 64 * kWavesPerBlock;
 constexpr int kWavesPerCU = 8;
 
-__device__ __forceinline__ int wave_max_i32(int v) {
-  for (int o = 32; o >= 1; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
-  return v;
-}
-
-// Walks one pair back from its optimum (i, j) and writes its CIGAR (in reverse, then flipped).
-template <int MODE>
-__device__ void walk_back(const uint32_t* __restrict__ dirs, int lane, int64_t max_m, int i, int j, uint32_t* cig,
-                          int64_t cap, int* q_begin, int* s_begin, int* n_runs) {
-  int state = 0;  // 0 = H, 1 = E, 2 = F
-  int64_t runs = 0;
-  uint32_t cur_op = 0xffu, cur_len = 0;
-  auto push = [&](uint32_t op) {
-    if (op == cur_op) {
-      ++cur_len;
-      return;
-    }
-    if (cur_len) {
-      if (runs < cap) cig[runs] = (cur_len << 4) | cur_op;
-      ++runs;
-    }
-    cur_op = op;
-    cur_len = 1;
-  };
-  auto code = [&](int ii, int jj) -> uint32_t {
-    const uint32_t w = dirs[((size_t)((ii - 1) / R) * (size_t)max_m + (size_t)(jj - 1)) * 64 + lane];
-    return (w >> (4 * ((ii - 1) % R))) & 15u;
-  };
-  for (;;) {
-    if (state == 0) {
-      if (i == 0 || j == 0) {
-        if (MODE == ALN_GLOBAL) {
-          while (j > 0) {
-            push(ALN_CIGAR_D);
-            --j;
-          }
-          while (i > 0) {
-            push(ALN_CIGAR_I);
-            --i;
-          }
-        }
-        break;
-      }
-      const uint32_t hs = code(i, j) & 3u;
-      if (hs == 3u) break;
-      if (hs == 0u) {
-        push(ALN_CIGAR_M);
-        --i;
-        --j;
-      } else {
-        state = (int)hs;
-      }
-    } else if (state == 1) {
-      const uint32_t c = code(i, j);
-      push(ALN_CIGAR_I);
-      if (c & 4u) state = 0;
-      --i;
-      if (i == 0) state = 0;
-    } else {
-      const uint32_t c = code(i, j);
-      push(ALN_CIGAR_D);
-      if (c & 8u) state = 0;
-      --j;
-      if (j == 0) state = 0;
-    }
-  }
-  if (cur_len) {
-    if (runs < cap) cig[runs] = (cur_len << 4) | cur_op;
-    ++runs;
-  }
-  if (runs <= cap) {
-    for (int64_t a = 0, b = runs - 1; a < b; ++a, --b) {
-      const uint32_t t = cig[a];
-      cig[a] = cig[b];
-      cig[b] = t;
-    }
-  }
-  *q_begin = i;
-  *s_begin = j;
-  *n_runs = (int)runs;
-}
-
 template <int MODE, bool AFFINE, bool TB>
 __global__ __launch_bounds__(kBlock) void batch_i32_kernel(
     const KParams P, const uint8_t* __restrict__ q, const int64_t* __restrict__ q_off, const uint8_t* __restrict__ s,
     const int64_t* __restrict__ s_off, int64_t n_pairs, int64_t max_n, int64_t max_m, aln_result_t* __restrict__ out,
     uint32_t* __restrict__ cigar, const int64_t* __restrict__ cigar_off, char* __restrict__ ws, size_t slab_bytes,
-    size_t rowbuf_bytes) {
+    size_t rowbuf_bytes, const int* __restrict__ idx, const int* __restrict__ idx_count, uint32_t extra_flags) {
   __shared__ int32_t tab[kTab * kTab];
   for (int k = threadIdx.x; k < kTab * kTab; k += blockDim.x) {
     const int a = k / kTab, b = k % kTab;
@@ -130,12 +48,15 @@ __global__ __launch_bounds__(kBlock) void batch_i32_kernel(
   char* slab = ws + wave * slab_bytes;
   int2* __restrict__ rowbuf = reinterpret_cast<int2*>(slab);
   uint32_t* __restrict__ dirs = reinterpret_cast<uint32_t*>(slab + rowbuf_bytes);
-  const int64_t groups = (n_pairs + 63) / 64;
+  // pairs come in input order, or from an index list whose length is a device value
+  const int64_t count = idx ? (int64_t)*idx_count : n_pairs;
+  const int64_t groups = (count + 63) / 64;
   const int32_t go = P.go, ge = P.ge, goe = P.goe;
 
   for (int64_t g = wave; g < groups; g += n_waves) {
-    const int64_t p = g * 64 + lane;
-    const bool active = p < n_pairs;
+    const int64_t slot = g * 64 + lane;
+    const bool active = slot < count;
+    const int64_t p = active ? (idx ? (int64_t)idx[slot] : slot) : 0;
     int64_t qb = 0, sb = 0;
     int n = 0, m = 0;
     uint32_t flags = 0;
@@ -228,9 +149,9 @@ __global__ __launch_bounds__(kBlock) void batch_i32_kernel(
               src = 1u;
             else
               src = 2u;
-            const uint32_t eo = AFFINE ? (uint32_t)(hup + goe == e) : 1u;
-            const uint32_t fo = AFFINE ? (uint32_t)(hlo + goe == ff) : 1u;
-            word |= (src | (eo << 2) | (fo << 3)) << (4 * r);
+            const uint32_t ee = AFFINE ? (uint32_t)(hup + goe != e) : 0u;
+            const uint32_t fe = AFFINE ? (uint32_t)(hlo + goe != ff) : 0u;
+            word |= (src | (ee << 2) | (fe << 3)) << (4 * r);
           }
           if (MODE == ALN_LOCAL) {
             if (h > bv[r]) {
@@ -313,13 +234,17 @@ __global__ __launch_bounds__(kBlock) void batch_i32_kernel(
       const int64_t c0 = cigar_off[p];
       const int64_t capw = cigar_off[p + 1] - c0;
       int qbeg, sbeg, runs;
-      walk_back<MODE>(dirs, lane, max_m, bi, bj, cigar + c0, capw, &qbeg, &sbeg, &runs);
+      auto code = [&](int ii, int jj) -> uint32_t {
+        const uint32_t w = dirs[((size_t)((ii - 1) / R) * (size_t)max_m + (size_t)(jj - 1)) * 64 + lane];
+        return (w >> (4 * ((ii - 1) % R))) & 15u;
+      };
+      walk_back<MODE>(code, bi, bj, cigar + c0, capw, &qbeg, &sbeg, &runs);
       res.q_begin = qbeg;
       res.s_begin = sbeg;
       res.cigar_len = runs;
       if (runs > capw) flags |= ALN_RES_CIGAR_TRUNC;
     }
-    res.flags = flags;
+    res.flags = flags | extra_flags;
     out[p] = res;
   }
 }
@@ -327,29 +252,30 @@ __global__ __launch_bounds__(kBlock) void batch_i32_kernel(
 template <int MODE, bool AFFINE, bool TB>
 void launch_one(const KParams& kp, const BatchPlan& pl, const uint8_t* q, const int64_t* q_off, const uint8_t* s,
                 const int64_t* s_off, aln_result_t* out, uint32_t* cigar, const int64_t* cigar_off, void* ws,
-                hipStream_t stream) {
+                const int* idx, const int* idx_count, uint32_t extra_flags, hipStream_t stream) {
   const size_t slab = pl.rowbuf_bytes + pl.dirs_bytes;
   const int blocks = (pl.n_waves + kWavesPerBlock - 1) / kWavesPerBlock;
+  ProfScope prof(TB ? "batch_i32_traceback" : "batch_i32_score", stream);
   hipLaunchKernelGGL((batch_i32_kernel<MODE, AFFINE, TB>), dim3(blocks), dim3(kBlock), 0, stream, kp, q, q_off, s,
                      s_off, pl.n_pairs, pl.max_n, pl.max_m, out, cigar, cigar_off, static_cast<char*>(ws), slab,
-                     pl.rowbuf_bytes);
+                     pl.rowbuf_bytes, idx, idx_count, extra_flags);
 }
 
 template <int MODE>
 void launch_mode(const KParams& kp, const BatchPlan& pl, const uint8_t* q, const int64_t* q_off, const uint8_t* s,
                  const int64_t* s_off, bool tb, aln_result_t* out, uint32_t* cigar, const int64_t* cigar_off,
-                 void* ws, hipStream_t stream) {
+                 void* ws, const int* idx, const int* idx_count, uint32_t extra_flags, hipStream_t stream) {
   const bool affine = kp.go != 0;
   if (affine) {
     if (tb)
-      launch_one<MODE, true, true>(kp, pl, q, q_off, s, s_off, out, cigar, cigar_off, ws, stream);
+      launch_one<MODE, true, true>(kp, pl, q, q_off, s, s_off, out, cigar, cigar_off, ws, idx, idx_count, extra_flags, stream);
     else
-      launch_one<MODE, true, false>(kp, pl, q, q_off, s, s_off, out, cigar, cigar_off, ws, stream);
+      launch_one<MODE, true, false>(kp, pl, q, q_off, s, s_off, out, cigar, cigar_off, ws, idx, idx_count, extra_flags, stream);
   } else {
     if (tb)
-      launch_one<MODE, false, true>(kp, pl, q, q_off, s, s_off, out, cigar, cigar_off, ws, stream);
+      launch_one<MODE, false, true>(kp, pl, q, q_off, s, s_off, out, cigar, cigar_off, ws, idx, idx_count, extra_flags, stream);
     else
-      launch_one<MODE, false, false>(kp, pl, q, q_off, s, s_off, out, cigar, cigar_off, ws, stream);
+      launch_one<MODE, false, false>(kp, pl, q, q_off, s, s_off, out, cigar, cigar_off, ws, idx, idx_count, extra_flags, stream);
   }
 }
 
@@ -382,17 +308,18 @@ aln_status_t plan_batch_i32(const KParams& kp, int64_t n_pairs, int64_t max_n, i
 
 aln_status_t launch_batch_i32(const KParams& kp, const BatchPlan& pl, const uint8_t* q, const int64_t* q_off,
                               const uint8_t* s, const int64_t* s_off, bool tb, aln_result_t* out, uint32_t* cigar,
-                              const int64_t* cigar_off, void* ws, hipStream_t stream) {
+                              const int64_t* cigar_off, void* ws, const int* idx, const int* idx_count,
+                              uint32_t extra_flags, hipStream_t stream) {
   if (pl.n_pairs == 0) return ALN_OK;
   switch (kp.mode) {
     case ALN_GLOBAL:
-      launch_mode<ALN_GLOBAL>(kp, pl, q, q_off, s, s_off, tb, out, cigar, cigar_off, ws, stream);
+      launch_mode<ALN_GLOBAL>(kp, pl, q, q_off, s, s_off, tb, out, cigar, cigar_off, ws, idx, idx_count, extra_flags, stream);
       break;
     case ALN_LOCAL:
-      launch_mode<ALN_LOCAL>(kp, pl, q, q_off, s, s_off, tb, out, cigar, cigar_off, ws, stream);
+      launch_mode<ALN_LOCAL>(kp, pl, q, q_off, s, s_off, tb, out, cigar, cigar_off, ws, idx, idx_count, extra_flags, stream);
       break;
     default:
-      launch_mode<ALN_SEMIGLOBAL>(kp, pl, q, q_off, s, s_off, tb, out, cigar, cigar_off, ws, stream);
+      launch_mode<ALN_SEMIGLOBAL>(kp, pl, q, q_off, s, s_off, tb, out, cigar, cigar_off, ws, idx, idx_count, extra_flags, stream);
       break;
   }
   return hipGetLastError() == hipSuccess ? ALN_OK : ALN_E_DEVICE;

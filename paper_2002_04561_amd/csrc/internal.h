@@ -41,6 +41,55 @@ struct BatchPlan {
   size_t total_bytes;
 };
 
+// Brackets the kernels enqueued in its lifetime with timing events when profiling is enabled.
+class ProfScope {
+ public:
+  ProfScope(const char* name, hipStream_t stream);
+  ~ProfScope();
+  ProfScope(const ProfScope&) = delete;
+  ProfScope& operator=(const ProfScope&) = delete;
+
+ private:
+  int token_;
+  hipStream_t stream_;
+};
+
+// One pair handled by the wavefront engine.
+struct WfPair {
+  int64_t q_off, s_off;  // offsets of the pair's codes in the concatenated q / s arrays
+  int32_t n, m;
+  int32_t nb;            // bands of the pair
+  int32_t out_idx;       // index of the pair's aln_result_t
+  int64_t item0;         // global index of the pair's first band
+  int64_t row_off;       // offset (int2 units) of the pair's two bottom-row slots, 2 * (m + 1)
+};
+
+// Device views of the wavefront engine's workspace.
+struct WfWs {
+  WfPair* pairs;     // [n_pairs], item0 ascending
+  int2* rows;        // row slots of all pairs
+  int* flags;        // [n_items] columns of each band's bottom row published so far
+  int4* band_res;    // [n_items] (score, i, j, flags) optimum of each band
+  int64_t* ticket;   // item dispenser
+  int64_t* n_items;  // total bands (device value, written by the planner)
+  int* n_pairs;      // pairs in the table (device value)
+  int* error;        // set when a bounded wait gives up
+};
+
+struct WfOffsets {
+  size_t pairs, rows, flags, res, misc;
+};
+
+struct LongPlan {
+  int64_t nb;
+  int n_waves;
+  WfOffsets off;
+  size_t total_bytes;
+};
+
+constexpr int kWfR = 4;             // rows per lane in the wavefront engine
+constexpr int kWfBand = 64 * kWfR;  // rows per band
+
 aln_status_t make_params(const aln_scoring_t* sc, KParams* kp);
 int device_cu_count();
 
@@ -49,6 +98,55 @@ aln_status_t plan_batch_i32(const KParams& kp, int64_t n_pairs, int64_t max_n, i
                             BatchPlan* plan);
 aln_status_t launch_batch_i32(const KParams& kp, const BatchPlan& plan, const uint8_t* q, const int64_t* q_off,
                               const uint8_t* s, const int64_t* s_off, bool traceback, aln_result_t* out,
-                              uint32_t* cigar, const int64_t* cigar_off, void* ws, hipStream_t stream);
+                              uint32_t* cigar, const int64_t* cigar_off, void* ws, const int* idx,
+                              const int* idx_count, uint32_t extra_flags, hipStream_t stream);
+
+// batch_i16.hip
+struct BatchPlan16 {
+  int64_t n_pairs, max_n, max_m;
+  int R;
+  int n_waves;
+  size_t rowbuf_bytes, slab_bytes, total_bytes;
+};
+struct I16Args {
+  const uint8_t* q;
+  const int64_t* q_off;
+  const uint8_t* s;
+  const int64_t* s_off;
+  aln_result_t* out;
+  uint32_t* cigar;
+  const int64_t* cigar_off;
+  void* ws;
+  const int* idx;
+  const int* idx_count;
+  int* redo_idx;
+  int* redo_cnt;
+  int force16;
+};
+aln_status_t plan_batch_i16(const KParams& kp, int64_t n_pairs, int64_t max_n, int64_t max_m, bool tb,
+                            BatchPlan16* plan);
+aln_status_t launch_batch_i16(const KParams& kp, const BatchPlan16& plan, const I16Args& args, bool tb,
+                              hipStream_t stream);
+
+// wf_i32.hip
+int wf_waves();
+size_t wf_layout(int64_t max_pairs, int64_t max_items, int64_t row_words, WfOffsets* o);
+WfWs wf_view(void* base, const WfOffsets& o);
+aln_status_t launch_wf_i32(const KParams& kp, const WfWs& W, const uint8_t* q, const uint8_t* s, aln_result_t* out,
+                           int max_waves, hipStream_t stream);
+aln_status_t plan_long(int64_t n, int64_t m, LongPlan* plan);
+aln_status_t launch_long(const KParams& kp, const LongPlan& plan, const uint8_t* q, int64_t n, const uint8_t* s,
+                         int64_t m, aln_result_t* out, void* ws, hipStream_t stream);
+
+// batch_plan.hip
+struct SplitPlan {
+  int64_t big_cells;  // pairs with n*m >= big_cells go to the wavefront engine
+  WfOffsets wf;
+  size_t off_small_idx, off_small_cnt, wf_base, total_bytes;
+  int wf_waves;
+};
+aln_status_t plan_split(int64_t n_pairs, int64_t total_q, int64_t total_s, SplitPlan* sp);
+void launch_split(const SplitPlan& sp, int64_t n_pairs, const int64_t* q_off, const int64_t* s_off, int64_t max_n,
+                  int64_t max_m, void* ws, hipStream_t stream);
 
 }  // namespace mialign

@@ -1,0 +1,471 @@
+// Intra-sequence wavefront engine, 32-bit lanes: bands of rows relaxed as anti-diagonal fronts.
+//
+// A work item is one band (BH = 64*R rows) of one pair.  A wave relaxes a band:
+// lane l owns R consecutive rows and works on column j = t - l + 1 at step t,
+// so the 64 lanes sweep the band as an anti-diagonal front (cells on one
+// anti-diagonal are independent, AnySeq Sec. III-A).  The lane above hands its
+// bottom-row H and E (and the subject letter) down with a DPP wave_shr:1 move
+// each step; lane 0 reads the band's top row, lane 63 emits the band's bottom
+// row through a DPP wave_shl:1 shift register that is stored every 64 steps.
+//
+// Items are handed out in order from one atomic ticket to persistent waves, so
+// several pairs of different sizes share the device the way the paper's
+// dynamic wavefront shares its queue between alignments (Sec. IV-A).  A band's
+// bottom row goes to one of two row slots of its pair in HBM; a per-item
+// progress counter, published with release semantics, tells the next band how
+// many columns are ready (the tile border publication of Sec. IV-B, with flags
+// instead of one kernel launch per tile diagonal).  Two slots suffice: band
+// b+2 can only write column c after band b+1 has consumed column c of the
+// slot, by the chain of dependencies.  Band b+1 is only handed out after band
+// b, so every wait is on a band that is already running; every wait is also
+// bounded -- a wave that spins too long raises an error flag and leaves, so
+// the grid always drains.
+#include "internal.h"
+
+namespace mialign {
+namespace {
+
+constexpr int kWfWavesPerBlock = 4;
+constexpr int kWfBlock = 64 * kWfWavesPerBlock;
+constexpr int kWfWavesPerCU = 4;
+constexpr long long kSpinLimit = 1ll << 25;
+
+__device__ __forceinline__ int dpp_shr1(int old, int src) {
+  return __builtin_amdgcn_update_dpp(old, src, 0x138, 0xf, 0xf, false);  // wave_shr:1, lane 0 keeps old
+}
+__device__ __forceinline__ int dpp_shl1(int old, int src) {
+  return __builtin_amdgcn_update_dpp(old, src, 0x130, 0xf, 0xf, false);  // wave_shl:1, lane 63 keeps old
+}
+
+// (score, i, j) order of optima: larger score, then smaller i, then smaller j.
+__device__ __forceinline__ bool better(int s1, int i1, int j1, int s2, int i2, int j2) {
+  return s1 > s2 || (s1 == s2 && (i1 < i2 || (i1 == i2 && j1 < j2)));
+}
+
+template <int MODE, bool AFFINE, bool SMALL, int R>
+__global__ __launch_bounds__(kWfBlock) void wf_i32_kernel(const KParams P, const uint8_t* __restrict__ Q,
+                                                          const uint8_t* __restrict__ S, WfWs W) {
+  __shared__ int32_t tab[kTab * kTab];
+  if (!SMALL) {
+    for (int k = threadIdx.x; k < kTab * kTab; k += blockDim.x) {
+      const int a = k / kTab, b = k % kTab;
+      tab[k] = (a >= P.alphabet || b >= P.alphabet) ? -kBig32 : (int32_t)P.sig[a * kMaxAlphabet + b];
+    }
+    __syncthreads();
+  }
+  constexpr int BH = 64 * R;
+  const int lane = threadIdx.x & 63;
+  const int32_t go = P.go, ge = P.ge, goe = P.goe;
+  const int np = *W.n_pairs;
+  const int64_t n_items = *W.n_items;
+
+  for (;;) {
+    int64_t t = 0;
+    if (lane == 0) t = (int64_t)atomicAdd(reinterpret_cast<unsigned long long*>(W.ticket), 1ull);
+    t = __shfl(t, 0, 64);
+    if (t >= n_items) break;
+    if (__hip_atomic_load(W.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+    // the pair owning item t: last k with pairs[k].item0 <= t
+    int lo = 0, hi = np - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (W.pairs[mid].item0 <= t)
+        lo = mid;
+      else
+        hi = mid - 1;
+    }
+    const WfPair pr = W.pairs[lo];
+    const int b = (int)(t - pr.item0);
+    const int n = pr.n, m = pr.m, nb = pr.nb;
+    const uint8_t* __restrict__ q = Q + pr.q_off;
+    const uint8_t* __restrict__ s = S + pr.s_off;
+    const int64_t ld = (int64_t)m + 1;
+
+    const int i0 = b * BH;
+    int prof[R];  // SMALL: 4 bytes sigma(q_i, a); else: q_i * kTab
+    int32_t hl[R], f[R], bv[R];
+    int bj[R];
+    bool bad = false;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int i = i0 + lane * R + r + 1;
+      int c = kPad;
+      if (i <= n) {
+        c = q[i - 1];
+        if (c >= P.alphabet) {
+          bad = true;
+          c = kPad;
+        }
+      }
+      if (SMALL) {
+        uint32_t w = 0;
+        for (int a = 0; a < 4; ++a) {
+          const int v = (c < P.alphabet && a < P.alphabet) ? (int)P.sig[c * kMaxAlphabet + a] : -128;
+          w |= ((uint32_t)(v & 0xff)) << (8 * a);
+        }
+        prof[r] = (int)w;
+      } else {
+        prof[r] = c * kTab;
+      }
+      hl[r] = (MODE == ALN_GLOBAL) ? go + i * ge : 0;
+      f[r] = kNeg32;
+      bv[r] = kNeg32;
+      bj[r] = 0;
+    }
+    const int irow0 = i0 + lane * R;  // the row just above this lane's first row
+    int32_t diag = (MODE == ALN_GLOBAL && irow0 > 0) ? go + irow0 * ge : 0;
+    int32_t bot_h = 0, bot_e = kNeg32, cur_c = 0, out_h = 0, out_e = 0;
+    // semi-global: the band holding row n tracks row n's running maximum
+    const bool last_band = (b == nb - 1);
+    int32_t brow = 0;
+    int browj = 0;
+    const int rn = n - 1 - irow0;  // index of row n among this lane's rows
+
+    int2* __restrict__ prev = W.rows + pr.row_off + (int64_t)((b + 1) & 1) * ld;
+    int2* __restrict__ cur = W.rows + pr.row_off + (int64_t)(b & 1) * ld;
+    int seen = 0;  // columns of the previous band known to be published
+    bool failed = false;
+
+    const int steps = m + 63;
+    for (int tb = 0; tb < steps; tb += 64) {
+      // lane-0 inputs for steps tb..tb+63 (columns tb+1..tb+64)
+      const int col_in = tb + 1 + lane;
+      int sreg = 0;
+      if (col_in <= m) {
+        sreg = s[col_in - 1];
+        if (sreg >= P.alphabet) {
+          bad = true;
+          sreg = SMALL ? 0 : kPad;
+        }
+      }
+      if (SMALL) sreg *= 8;
+      int32_t th, te;
+      if (b == 0) {
+        th = (MODE == ALN_GLOBAL) ? go + col_in * ge : 0;
+        te = kNeg32;
+      } else {
+        const int need = min(tb + 64, m);
+        if (seen < need) {
+          int v = 0;
+          if (lane == 0) {
+            long long spins = 0;
+            for (;;) {
+              v = __hip_atomic_load(W.flags + (t - 1), __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+              if (v >= need) break;
+              if (++spins > kSpinLimit || __hip_atomic_load(W.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                v = -1;
+                break;
+              }
+              __builtin_amdgcn_s_sleep(2);
+            }
+          }
+          v = __shfl(v, 0, 64);
+          if (v < 0) {
+            if (lane == 0) __hip_atomic_store(W.error, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            failed = true;
+            break;
+          }
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+          seen = v;
+        }
+        th = 0;
+        te = kNeg32;
+        if (col_in <= m) {
+          const long long pv = __hip_atomic_load(reinterpret_cast<long long*>(prev + col_in), __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT);
+          th = (int32_t)(pv & 0xffffffffll);
+          te = (int32_t)(pv >> 32);
+        }
+      }
+#pragma unroll 4
+      for (int u = 0; u < 64; ++u) {
+        const int j = tb + u - lane + 1;
+        const int in_h = dpp_shr1(__builtin_amdgcn_readlane(th, u), bot_h);
+        const int in_e = dpp_shr1(__builtin_amdgcn_readlane(te, u), bot_e);
+        const int in_c = dpp_shr1(__builtin_amdgcn_readlane(sreg, u), cur_c);
+        cur_c = in_c;
+        if (j >= 1 && j <= m) {
+          int32_t hd = diag, hup = in_h, eup = in_e;
+          int32_t hn = 0;
+#pragma unroll
+          for (int r = 0; r < R; ++r) {
+            const int32_t hlo = hl[r];
+            const int32_t e = AFFINE ? max(eup + ge, hup + goe) : hup + ge;
+            const int32_t ff = AFFINE ? max(f[r] + ge, hlo + goe) : hlo + ge;
+            const int32_t sg = SMALL ? __builtin_amdgcn_sbfe(prof[r], in_c, 8) : tab[prof[r] + in_c];
+            int32_t h = max(hd + sg, max(e, ff));
+            if (MODE == ALN_LOCAL) {
+              h = max(h, 0);
+              if (h > bv[r]) {
+                bv[r] = h;
+                bj[r] = j;
+              }
+            }
+            if (MODE == ALN_SEMIGLOBAL && r == rn) hn = h;
+            f[r] = ff;
+            hl[r] = h;
+            hd = hlo;
+            hup = h;
+            eup = e;
+          }
+          if (MODE == ALN_SEMIGLOBAL && last_band && rn >= 0 && rn < R && hn > brow) {
+            brow = hn;
+            browj = j;
+          }
+          bot_h = hup;
+          bot_e = eup;
+          diag = in_h;
+        }
+        out_h = dpp_shl1(bot_h, out_h);
+        out_e = dpp_shl1(bot_e, out_e);
+      }
+      // lane u now holds lane 63's outputs of step tb+u, i.e. column tb+u-62
+      if (b + 1 < nb) {
+        const int col_out = tb + lane - 62;
+        if (col_out >= 1 && col_out <= m) {
+          const long long pv = ((long long)(uint32_t)out_h) | ((long long)out_e << 32);
+          __hip_atomic_store(reinterpret_cast<long long*>(cur + col_out), pv, __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+        }
+        const int published = min(tb + 1, m);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        if (published >= 1 && lane == 0)
+          __hip_atomic_store(W.flags + t, published, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+    }
+
+    // band optimum: (score, i, j) over this lane's rows, then across the wave
+    int bs = kNeg32, bi = 0, bjj = 0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int i = irow0 + r + 1;
+      if (i > n) continue;
+      int sc = 0, jj = 0;
+      bool cand = false;
+      if (MODE == ALN_LOCAL) {
+        sc = bv[r];
+        jj = bj[r];
+        cand = sc > 0;
+      } else if (MODE == ALN_SEMIGLOBAL) {
+        sc = hl[r];  // H(i, m): last-column candidate; row n is handled below
+        jj = m;
+        cand = (i < n);
+      } else {
+        sc = hl[r];
+        jj = m;
+        cand = (i == n);
+      }
+      if (cand && better(sc, i, jj, bs, bi, bjj)) {
+        bs = sc;
+        bi = i;
+        bjj = jj;
+      }
+    }
+    if (MODE == ALN_SEMIGLOBAL && last_band && rn >= 0 && rn < R && better(brow, n, browj, bs, bi, bjj)) {
+      bs = brow;
+      bi = n;
+      bjj = browj;
+    }
+    for (int o = 32; o >= 1; o >>= 1) {
+      const int s2 = __shfl_xor(bs, o, 64), i2 = __shfl_xor(bi, o, 64), j2 = __shfl_xor(bjj, o, 64);
+      if (better(s2, i2, j2, bs, bi, bjj)) {
+        bs = s2;
+        bi = i2;
+        bjj = j2;
+      }
+    }
+    const bool anybad = __any(bad);
+    if (lane == 0) W.band_res[t] = make_int4(bs, bi, bjj, (anybad ? 1 : 0) | (failed ? 2 : 0));
+  }
+}
+
+// One wave per pair: reduces the pair's band optima into its aln_result_t.
+__global__ __launch_bounds__(256) void wf_finish_kernel(const KParams P, WfWs W, aln_result_t* __restrict__ out) {
+  const int lane = threadIdx.x & 63;
+  const int np = *W.n_pairs;
+  const bool err = __hip_atomic_load(W.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+  for (int k = blockIdx.x * 4 + (threadIdx.x >> 6); k < np; k += gridDim.x * 4) {
+    const WfPair pr = W.pairs[k];
+    int bs = kNeg32, bi = 0, bj = 0, flag = 0;
+    for (int b = lane; b < pr.nb; b += 64) {
+      const int4 v = W.band_res[pr.item0 + b];
+      flag |= v.w;
+      if (better(v.x, v.y, v.z, bs, bi, bj)) {
+        bs = v.x;
+        bi = v.y;
+        bj = v.z;
+      }
+    }
+    for (int o = 32; o >= 1; o >>= 1) {
+      const int s2 = __shfl_xor(bs, o, 64), i2 = __shfl_xor(bi, o, 64), j2 = __shfl_xor(bj, o, 64);
+      flag |= __shfl_xor(flag, o, 64);
+      if (better(s2, i2, j2, bs, bi, bj)) {
+        bs = s2;
+        bi = i2;
+        bj = j2;
+      }
+    }
+    if (lane != 0) continue;
+    const int n = pr.n, m = pr.m;
+    aln_result_t r;
+    r.q_begin = -1;
+    r.s_begin = -1;
+    r.cigar_len = 0;
+    r.reserved = 0;
+    r.flags = 0;
+    if (P.mode == ALN_GLOBAL) {
+      r.q_end = n;
+      r.s_end = m;
+      r.score = (n == 0 || m == 0) ? ((n + m > 0) ? P.go + (n + m) * P.ge : 0) : bs;
+    } else if (n == 0 || m == 0 || bs < 0 || (bs == 0 && P.mode == ALN_LOCAL)) {
+      // local: the empty alignment at (0,0); semi-global: the first candidate (0, m), or (0, 0) if a side is empty
+      r.score = 0;
+      r.q_end = 0;
+      r.s_end = (P.mode == ALN_SEMIGLOBAL && n > 0) ? m : 0;
+    } else if (P.mode == ALN_SEMIGLOBAL && bs == 0) {
+      r.score = 0;  // (0, m) precedes every other candidate in row-major order
+      r.q_end = 0;
+      r.s_end = m;
+    } else {
+      r.score = bs;
+      r.q_end = bi;
+      r.s_end = bj;
+    }
+    if (err || (flag & 2)) r.flags |= ALN_RES_DEVICE_ERROR;
+    if (flag & 1) {
+      r.flags |= ALN_RES_BAD_CODE;
+      r.score = 0;
+      r.q_end = 0;
+      r.s_end = 0;
+    }
+    out[pr.out_idx] = r;
+  }
+}
+
+// Clears the progress flags of every item and the ticket before a wavefront launch.
+__global__ void wf_reset_kernel(WfWs W) {
+  const int64_t n_items = *W.n_items;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n_items; k += (int64_t)gridDim.x * blockDim.x)
+    W.flags[k] = 0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    *W.ticket = 0;
+    *W.error = 0;
+  }
+}
+
+// align_long: describes the single pair as the only entry of the pair table.
+__global__ void wf_single_pair_kernel(WfWs W, int n, int m, int band_rows) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    WfPair p;
+    p.q_off = 0;
+    p.s_off = 0;
+    p.n = n;
+    p.m = m;
+    p.nb = (n > 0 && m > 0) ? (n + band_rows - 1) / band_rows : 0;
+    p.item0 = 0;
+    p.row_off = 0;
+    p.out_idx = 0;
+    W.pairs[0] = p;
+    *W.n_pairs = 1;
+    *W.n_items = p.nb;
+  }
+}
+
+template <int MODE, bool AFFINE, bool SMALL>
+void launch_wf_t(const KParams& kp, const uint8_t* q, const uint8_t* s, const WfWs& W, int n_waves,
+                 hipStream_t stream) {
+  const int blocks = (n_waves + kWfWavesPerBlock - 1) / kWfWavesPerBlock;
+  ProfScope prof("wavefront_i32", stream);
+  hipLaunchKernelGGL((wf_i32_kernel<MODE, AFFINE, SMALL, kWfR>), dim3(blocks), dim3(kWfBlock), 0, stream, kp, q, s,
+                     W);
+}
+
+template <int MODE>
+void launch_wf_m(const KParams& kp, const uint8_t* q, const uint8_t* s, const WfWs& W, int nw, hipStream_t st) {
+  const bool affine = kp.go != 0, small = kp.alphabet <= 4;
+  if (affine && small) launch_wf_t<MODE, true, true>(kp, q, s, W, nw, st);
+  if (affine && !small) launch_wf_t<MODE, true, false>(kp, q, s, W, nw, st);
+  if (!affine && small) launch_wf_t<MODE, false, true>(kp, q, s, W, nw, st);
+  if (!affine && !small) launch_wf_t<MODE, false, false>(kp, q, s, W, nw, st);
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+}  // namespace
+
+int wf_waves() {
+  const int cus = device_cu_count();
+  return cus > 0 ? cus * kWfWavesPerCU : -1;
+}
+
+size_t wf_layout(int64_t max_pairs, int64_t max_items, int64_t row_words, WfOffsets* o) {
+  size_t off = 0;
+  o->pairs = off;
+  off += align256((size_t)max_pairs * sizeof(WfPair));
+  o->rows = off;
+  off += align256((size_t)row_words * sizeof(int2));
+  o->flags = off;
+  off += align256((size_t)(max_items + 1) * sizeof(int));
+  o->res = off;
+  off += align256((size_t)(max_items + 1) * sizeof(int4));
+  o->misc = off;
+  off += 256;
+  return off;
+}
+
+WfWs wf_view(void* base_, const WfOffsets& o) {
+  char* base = static_cast<char*>(base_);
+  WfWs W;
+  W.pairs = reinterpret_cast<WfPair*>(base + o.pairs);
+  W.rows = reinterpret_cast<int2*>(base + o.rows);
+  W.flags = reinterpret_cast<int*>(base + o.flags);
+  W.band_res = reinterpret_cast<int4*>(base + o.res);
+  W.ticket = reinterpret_cast<int64_t*>(base + o.misc);
+  W.n_items = reinterpret_cast<int64_t*>(base + o.misc + 8);
+  W.n_pairs = reinterpret_cast<int*>(base + o.misc + 16);
+  W.error = reinterpret_cast<int*>(base + o.misc + 20);
+  return W;
+}
+
+aln_status_t launch_wf_i32(const KParams& kp, const WfWs& W, const uint8_t* q, const uint8_t* s,
+                           aln_result_t* out, int max_waves, hipStream_t stream) {
+  hipLaunchKernelGGL(wf_reset_kernel, dim3(256), dim3(256), 0, stream, W);
+  switch (kp.mode) {
+    case ALN_GLOBAL:
+      launch_wf_m<ALN_GLOBAL>(kp, q, s, W, max_waves, stream);
+      break;
+    case ALN_LOCAL:
+      launch_wf_m<ALN_LOCAL>(kp, q, s, W, max_waves, stream);
+      break;
+    default:
+      launch_wf_m<ALN_SEMIGLOBAL>(kp, q, s, W, max_waves, stream);
+      break;
+  }
+  hipLaunchKernelGGL(wf_finish_kernel, dim3(256), dim3(256), 0, stream, kp, W, out);
+  return hipGetLastError() == hipSuccess ? ALN_OK : ALN_E_DEVICE;
+}
+
+// ---------------------------------------------------------------------------------------------
+// aln_align_long: the engine on one pair.
+// ---------------------------------------------------------------------------------------------
+aln_status_t plan_long(int64_t n, int64_t m, LongPlan* pl) {
+  pl->nb = (n + kWfBand - 1) / kWfBand;
+  const int nw = wf_waves();
+  if (nw <= 0) return ALN_E_DEVICE;
+  int64_t waves = nw;
+  const int64_t want = (pl->nb + kWfWavesPerBlock - 1) / kWfWavesPerBlock * kWfWavesPerBlock;
+  if (want < waves) waves = want;
+  if (waves < kWfWavesPerBlock) waves = kWfWavesPerBlock;
+  pl->n_waves = (int)waves;
+  pl->total_bytes = wf_layout(1, pl->nb, 2 * (m + 1), &pl->off);
+  return ALN_OK;
+}
+
+aln_status_t launch_long(const KParams& kp, const LongPlan& pl, const uint8_t* q, int64_t n, const uint8_t* s,
+                         int64_t m, aln_result_t* out, void* ws, hipStream_t stream) {
+  WfWs W = wf_view(ws, pl.off);
+  hipLaunchKernelGGL(wf_single_pair_kernel, dim3(1), dim3(64), 0, stream, W, (int)n, (int)m, kWfBand);
+  return launch_wf_i32(kp, W, q, s, out, pl.n_waves, stream);
+}
+
+}  // namespace mialign

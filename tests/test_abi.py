@@ -47,5 +47,5 @@ def test_scoring_validation_on_host():
     for sc, e in zip(bad, expect):
         out = ctypes.c_size_t(0)
         c = sc.c()
-        st = aln.lib().aln_batch_workspace_size(ctypes.byref(c), 10, 100, 100, 0, ctypes.byref(out))
+        st = aln.lib().aln_batch_workspace_size(ctypes.byref(c), 10, 100, 100, 1000, 1000, 0, ctypes.byref(out))
         assert st == e, (sc, st)

@@ -88,3 +88,71 @@ def test_bad_codes_flagged(gpu):
     ores, ocig = run_oracle(w, True)
     bad = compare(w, gres, gcig, ores, ocig, "bad")
     assert not bad, "\n".join(bad)
+
+
+@pytest.mark.parametrize("mode", [0, 1, 2], ids=["global", "local", "semi"])
+@pytest.mark.parametrize("scheme", ["prot_affine", "dna_affine", "dna_linear"])
+def test_uneven_split_score_only(gpu, mode, scheme):
+    """Log-uniform lengths 64..3000: pairs with n*m >= 2^20 take the band wavefront, the rest one lane each."""
+    import paper_2002_04561_amd as aln
+    A, ma, mi, sub, go, ge = SCHEMES[scheme]
+    rng = np.random.default_rng(300 + mode)
+    lens = np.rint(np.exp(rng.uniform(np.log(64), np.log(3000), (120, 2)))).astype(int)
+    qs = [rng.integers(0, A, a, dtype=np.uint8) for a, _ in lens]
+    ss = [synth.mutate_geometric(rng, qs[k], 0.1, 0.02, 2.0, A)[:b] if k % 3 == 0 else
+          rng.integers(0, A, b, dtype=np.uint8) for k, (_, b) in enumerate(lens)]
+    q, qo = synth.pack(qs)
+    s, so = synth.pack(ss)
+    w = synth.Workload("uneven", mode, A, go, ge, q, qo, s, so, match=ma, mismatch=mi, subst=sub)
+    n, m = w.lengths()
+    assert np.any(n * m >= (1 << 20)) and np.any(n * m < (1 << 20))
+    gres, _ = run_gpu(w, aln.SCORE_ONLY)
+    ores, _ = run_oracle(w, False)
+    bad = compare(w, gres, None, ores, None, "uneven")
+    assert not bad, "\n".join(bad[:10])
+
+
+@pytest.mark.parametrize("mode", [0, 1, 2], ids=["global", "local", "semi"])
+@pytest.mark.parametrize("tb", [False, True], ids=["score", "traceback"])
+def test_overflow_redo(gpu, mode, tb):
+    """Pairs whose scores leave the 16-bit range: identical 300-letter pairs at match +120 (36000 > 32767), mixed
+    with ordinary pairs.  Local pairs run in 16 bits under ALN_FORCE_INT16, saturate and are redone; every pair
+    must come back bit-exact, and exactly the big-score pairs carry ALN_RES_INT32_REDO."""
+    import paper_2002_04561_amd as aln
+    rng = np.random.default_rng(9 + mode)
+    qs, ss, hot = [], [], []
+    for k in range(200):
+        if k % 7 == 0:
+            a = rng.integers(0, 4, 300, dtype=np.uint8)
+            qs.append(a)
+            ss.append(a.copy())
+            hot.append(True)
+        else:
+            qs.append(rng.integers(0, 4, int(rng.integers(0, 280)), dtype=np.uint8))
+            ss.append(rng.integers(0, 4, int(rng.integers(0, 280)), dtype=np.uint8))
+            hot.append(False)
+    q, qo = synth.pack(qs)
+    s, so = synth.pack(ss)
+    w = synth.Workload("overflow", mode, 4, -30, -20, q, qo, s, so, match=120, mismatch=-40)
+    ores, ocig = run_oracle(w, tb)
+    for extra in (0, aln.FORCE_INT16):
+        flags = (aln.TRACEBACK if tb else aln.SCORE_ONLY) | extra
+        gres, gcig = run_gpu(w, flags)
+        bad = compare(w, gres, gcig, ores, ocig, "overflow")
+        assert not bad, "\n".join(bad[:10])
+        redo = (gres["flags"] & aln.RES_INT32_REDO) != 0
+        assert np.all(redo[np.array(hot)]), "big-score pairs must be recomputed in 32 bits"
+        assert int(np.sum(ores["score"][np.array(hot)] > 32767)) == int(np.sum(hot))
+
+
+@pytest.mark.parametrize("mode", [0, 1, 2], ids=["global", "local", "semi"])
+@pytest.mark.parametrize("scheme", ["dna_affine", "prot_affine", "dna_linear"])
+def test_int16_equals_int32(gpu, mode, scheme):
+    """The packed 16-bit path and ALN_FORCE_INT32 give identical results (scores, ends, CIGARs)."""
+    import paper_2002_04561_amd as aln
+    w = _workload(500 + mode, 300, 0, 260, mode, scheme)
+    a, ac = run_gpu(w, aln.TRACEBACK)
+    b, bc = run_gpu(w, aln.TRACEBACK | aln.FORCE_INT32)
+    for k in range(w.n_pairs):
+        assert tuple(a[k])[:6] == tuple(b[k])[:6] and ac[k] == bc[k], k
+    assert not np.any(a["flags"] & aln.RES_INT32_REDO)

@@ -1,0 +1,98 @@
+"""GPU parity of aln_align_long (one pair, band wavefront) against the oracle."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def _run(q, s, mode, A, go, ge, match=None, mismatch=None, subst=None):
+    import torch
+
+    import paper_2002_04561_amd as aln
+    sc = aln.Scoring(mode, A, go, ge, match=match or 0, mismatch=mismatch or 0, subst=subst)
+    qd = torch.from_numpy(np.ascontiguousarray(q, dtype=np.uint8) if len(q) else np.zeros(1, np.uint8)).cuda()
+    sd = torch.from_numpy(np.ascontiguousarray(s, dtype=np.uint8) if len(s) else np.zeros(1, np.uint8)).cuda()
+    la = aln.LongAligner(sc, qd[:len(q)], sd[:len(s)])
+    la.run()
+    torch.cuda.synchronize()
+    r = la.result()
+    return int(r["score"]), int(r["q_end"]), int(r["s_end"]), int(r["flags"])
+
+
+def _oracle(q, s, mode, A, go, ge, match=None, mismatch=None, subst=None):
+    if subst is not None:
+        sc = oracle.Scoring.matrix(mode, subst.astype(np.int32), go, ge)
+    else:
+        sc = oracle.Scoring.simple(mode, A, match, mismatch, go, ge)
+    r = oracle.align(sc, q, s, impl="linspace")
+    return r.score, r.q_end, r.s_end, 0
+
+
+SHAPES = [(1, 1), (5, 3), (63, 64), (64, 65), (255, 70), (256, 256), (257, 1000), (700, 40), (40, 700),
+          (1000, 1300), (1536, 900), (2049, 2500)]
+
+
+@pytest.mark.parametrize("mode", [0, 1, 2], ids=["global", "local", "semi"])
+@pytest.mark.parametrize("gap", [(0, -1), (-3, -1)], ids=["linear", "affine"])
+def test_long_dna_shapes(gpu, mode, gap):
+    rng = np.random.default_rng(40 + mode)
+    go, ge = gap
+    for (n, m) in SHAPES:
+        q = rng.integers(0, 4, n, dtype=np.uint8)
+        s = synth.mutate_geometric(rng, q, 0.05, 0.01, 3.0)[:m] if rng.random() < 0.6 else \
+            rng.integers(0, 4, m, dtype=np.uint8)
+        if len(s) < m:
+            s = np.concatenate([s, rng.integers(0, 4, m - len(s), dtype=np.uint8)])
+        got = _run(q, s, mode, 4, go, ge, match=2, mismatch=-3)
+        exp = _oracle(q, s, mode, 4, go, ge, match=2, mismatch=-3)
+        assert got == exp, (n, m, got, exp)
+
+
+@pytest.mark.parametrize("mode", [0, 1, 2], ids=["global", "local", "semi"])
+def test_long_protein_table(gpu, mode):
+    rng = np.random.default_rng(77)
+    sig = synth.protein_sigma(rng)
+    for (n, m) in [(300, 500), (1025, 777), (2000, 2100)]:
+        q = rng.integers(0, 20, n, dtype=np.uint8)
+        s = rng.integers(0, 20, m, dtype=np.uint8)
+        got = _run(q, s, mode, 20, -11, -1, subst=sig)
+        exp = _oracle(q, s, mode, 20, -11, -1, subst=sig)
+        assert got == exp, (n, m, got, exp)
+
+
+def test_long_empty_and_bad(gpu):
+    assert _run(np.zeros(0, np.uint8), np.array([1, 2], np.uint8), 0, 4, -3, -1, 2, -3)[:3] == (-5, 0, 2)
+    assert _run(np.array([1, 2], np.uint8), np.zeros(0, np.uint8), 1, 4, -3, -1, 2, -3)[:3] == (0, 0, 0)
+    got = _run(np.array([1, 7, 2], np.uint8), np.array([1, 2], np.uint8), 1, 4, -3, -1, 2, -3)
+    assert got[3] & 4
+
+
+def test_long_prefix_of_full_workload(gpu):
+    """The first 8192 rows of the 262144 x 262144 workload against the oracle (same seeded input)."""
+    w = synth.long_dna_local(seed=2, n=262144)
+    a, b = w.pair(0)
+    a = a[:8192]
+    b = b[:20000]
+    got = _run(a, b, 1, 4, -3, -1, 2, -3)
+    exp = _oracle(a, b, 1, 4, -3, -1, 2, -3)
+    assert got == exp
+
+
+@pytest.mark.slow
+def test_long_full_262144(gpu):
+    """The full 262144 x 262144 local affine pair against the stored oracle value."""
+    path = os.path.join(HERE, "golden", "long_local_262144.json")
+    if not os.path.exists(path):
+        pytest.skip("golden value not generated")
+    g = json.load(open(path))
+    w = synth.long_dna_local(seed=2, n=262144)
+    a, b = w.pair(0)
+    got = _run(a, b, 1, 4, -3, -1, 2, -3)
+    assert got[:3] == (g["score"], g["q_end"], g["s_end"])
