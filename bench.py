@@ -12,6 +12,9 @@ Workloads (synth/__init__.py has the recipes):
   reads    1,048,576 read/window pairs, semi-global affine (-5/-2, +1/-4), CIGAR for every pair
   protein  65,536 protein pairs, lengths log-uniform 64..16384, local affine (-11/-1), score-only
   nw1k     1 pair 1000 x 1000 DNA, global linear (+2/-1, gap -1), CIGAR
+  serve    a Poisson request stream through the continuous-batching server (paper_2002_04561_amd/serve.py):
+           80% read/window pairs with CIGARs, 19% protein pairs (lengths log-uniform 64..16384), 1% local
+           DNA pairs of 65536 x 65536; reports GCUPS over the run and p50/p99 latency per class
 """
 import argparse
 import json
@@ -122,12 +125,71 @@ def spot_check(w, res, cigars, idx):
     return "bit-exact on %d sampled pairs" % len(idx)
 
 
+def serve_stream(n_req, rate_hz, seed=5, long_len=65536):
+    """The request mix of the serving workload; arrivals are Poisson at rate_hz."""
+    import synth
+    from paper_2002_04561_amd.serve import Request
+    rng = np.random.default_rng(seed)
+    reads = synth.reads_semiglobal(seed=seed, n_pairs=n_req)
+    sig = synth.protein_sigma(rng)
+    reqs, t = [], 0.0
+    for k in range(n_req):
+        t += rng.exponential(1.0 / rate_hz)
+        u = rng.random()
+        if u < 0.8:
+            a, b = reads.pair(k)
+            reqs.append(Request(k, "read", a.copy(), b.copy(), t, traceback=True))
+        elif u < 0.99:
+            n, m = np.rint(np.exp(rng.uniform(np.log(64), np.log(16384), 2))).astype(int)
+            reqs.append(Request(k, "protein", rng.integers(0, 20, n, dtype=np.uint8),
+                                rng.integers(0, 20, m, dtype=np.uint8), t))
+        else:
+            a = rng.integers(0, 4, long_len, dtype=np.uint8)
+            b = synth.mutate_geometric(rng, a, 0.05, 0.01, 3.0)[:long_len]
+            if len(b) < long_len:
+                b = np.concatenate([b, rng.integers(0, 4, long_len - len(b), dtype=np.uint8)])
+            reqs.append(Request(k, "long", a, b, t, long=True))
+    return reqs, sig
+
+
+def run_serve(args):
+    import torch
+
+    import paper_2002_04561_amd as aln
+    import synth
+    from paper_2002_04561_amd.serve import AlignServer
+    reqs, sig = serve_stream(args.requests, args.rate)
+    sc = {"read": aln.Scoring(synth.SEMIGLOBAL, 4, -5, -2, match=1, mismatch=-4),
+          "protein": aln.Scoring(synth.LOCAL, 20, -11, -1, subst=sig),
+          "long": aln.Scoring(synth.LOCAL, 4, -3, -1, match=2, mismatch=-3)}
+    torch.cuda.set_device(0)
+    warm, _ = serve_stream(64, 1e6, seed=99, long_len=4096)
+    AlignServer(sc, budget_bytes=args.budget_gb << 30).run(warm, realtime=False)
+    srv = AlignServer(sc, budget_bytes=args.budget_gb << 30, streams=3, max_pairs=8192)
+    st = srv.run(reqs, realtime=True)
+    out = {
+        "metric": "GCUPS (batched vs plain, bit-exact) on one MI355X; p50/p99 request latency",
+        "value": round(st["gcups"], 2), "unit": "GCUPS", "n_gpus": 1, "steps": 1, "warmup": 1,
+        "ms_per_step": round(st["wall_s"] * 1e3, 1), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "int16+int32", "data": "synthetic (seeded generator)",
+        "config": {"workload": "serve", "requests": len(reqs), "rate_per_s": args.rate, "cells": st["cells"],
+                   "budget_bytes": st["budget_bytes"], "peak_bytes": st["peak_bytes"]},
+        "latency_ms": st["classes"],
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="reads", choices=["long", "reads", "protein", "nw1k"])
+    ap.add_argument("--workload", default="long", choices=["long", "reads", "protein", "nw1k", "serve"])
+    ap.add_argument("--requests", type=int, default=1000, help="serve: number of requests")
+    ap.add_argument("--rate", type=float, default=15.0, help="serve: Poisson arrival rate (requests/s)")
+    ap.add_argument("--budget-gb", type=int, default=64, help="serve: device memory budget (GiB)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run only a plain 1 GiB device-to-device copy (scale for rocprofv3 FETCH_SIZE/WRITE_SIZE)")
     ap.add_argument("--pairs", type=int, default=None, help="override the pair count of a batch workload")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
@@ -136,6 +198,19 @@ def main():
         print("bench.py runs on one GPU only: this build has no multi-GPU path (see DESIGN.md for how the "
               "work would shard)", file=sys.stderr)
         sys.exit(2)
+
+    if args.copy_calibration:
+        import torch
+        x = torch.ones(1 << 28, dtype=torch.int32, device="cuda")
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": 1 << 30, "copy_bytes_written": 1 << 30}))
+        return
+    if args.workload == "serve":
+        run_serve(args)
+        return
 
     import torch
 
@@ -152,7 +227,7 @@ def main():
     log("workload %s: %d pairs, %.4g cells, generated in %.1f s" % (w.name, w.n_pairs, cells, time.time() - t0))
     stream = torch.cuda.Stream()
     flags = aln.TRACEBACK if w.traceback else aln.SCORE_ONLY
-    long_path = (w.n_pairs == 1 and not w.traceback)
+    long_path = (w.n_pairs == 1)
     with torch.cuda.stream(stream):
         q, qo, s, so = aln.to_device(w)
         if long_path:
@@ -180,14 +255,17 @@ def main():
 
     res = ba.result().reshape(1) if long_path else ba.results()
     idx = sample_indices(w)
-    cigars = ba.cigars(idx) if w.traceback else None
+    if long_path:
+        cigars = {0: ba.cigar_runs()} if w.traceback else None
+    else:
+        cigars = ba.cigars(idx) if w.traceback else None
     check = "skipped" if args.no_check else spot_check(w, res, cigars, idx)
     log("parity:", check)
 
     gap = "linear" if w.gap_open == 0 else "affine"
     opc = OPS_PER_CELL[(MODE_NAME[w.mode], gap)]
-    dom = max(prof.items(), key=lambda kv: kv[1][1]) if prof else None
-    dtype = "int32"
+    dom = max(((k, v) for k, v in prof.items() if k != "plan"), key=lambda kv: kv[1][1]) if prof else None
+    dtype = "int16" if (dom and "i16" in dom[0]) else "int32"
     peak = PEAK_I32_TOPS if dtype == "int32" else PEAK_I16_TOPS
     roof = None
     if dom:
@@ -197,7 +275,8 @@ def main():
         achieved = opc * cells_per_launch / (per_launch_ms * 1e-3) / 1e12
         roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 2), "unit": "Tops/s",
                 "frac": round(achieved / peak, 4), "traffic": None, "kernel": dom[0],
-                "kernel_ms": round(per_launch_ms, 4), "ops_per_cell": opc}
+                "kernel_ms": round(per_launch_ms, 4), "ops_per_cell": opc,
+                "kernels_ms_per_step": {k: round(v[1] / args.steps, 4) for k, v in prof.items()}}
     out = {
         "metric": "GCUPS (batched vs plain, bit-exact) on one MI355X; p50/p99 request latency",
         "value": round(gcups, 2), "unit": "GCUPS", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,

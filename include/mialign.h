@@ -131,23 +131,27 @@ aln_status_t aln_align_batch(const aln_scoring_t* scoring, int64_t n_pairs, cons
                              int64_t total_s, uint32_t flags, aln_result_t* out, uint32_t* cigar,
                              const int64_t* cigar_off, void* workspace, size_t workspace_bytes, hipStream_t stream);
 
-/* Bytes of device workspace aln_align_long needs for an n x m problem. */
+/* Bytes of device workspace aln_align_long needs for an n x m problem and the given flags. */
 aln_status_t aln_long_workspace_size(const aln_scoring_t* scoring, int64_t n, int64_t m, uint32_t flags,
                                      size_t* bytes);
 
-/* Aligns one long pair with intra-sequence parallelism: the matrix is relaxed in bands of rows that
- * move as a wavefront across the device (AnySeq Sec. IV-B tiles relaxed along anti-diagonals, each
- * publishing its last row to the next).  Score and end cell only (q_begin = s_begin = -1).
+/* Aligns one long pair with intra-sequence parallelism: the matrix is relaxed in bands of 256 rows
+ * that move as a wavefront across the device (AnySeq Sec. IV-B: tiles relaxed along anti-diagonals,
+ * each publishing its last row to the next), all bands drawn from one device-side work queue.
  *   q             DEVICE  n uint8 codes;  s  DEVICE  m uint8 codes
- *   flags         ALN_SCORE_ONLY (ALN_TRACEBACK returns ALN_E_UNSUPPORTED)
- *   out           DEVICE  one aln_result_t
- *   workspace     DEVICE  at least aln_long_workspace_size(...) bytes, 256-byte aligned; it holds the
- *                         bottom row of every band, (n / 256) * (m + 1) * 8 bytes.
+ *   flags         ALN_SCORE_ONLY, or ALN_TRACEBACK to also write the canonical CIGAR
+ *   out           DEVICE  one aln_result_t (q_begin = s_begin = -1 when score-only)
+ *   cigar         DEVICE  CIGAR words, cigar_capacity of them (n + m always suffice); NULL when
+ *                         score-only.  A short buffer gives ALN_RES_CIGAR_TRUNC and the required count.
+ *   workspace     DEVICE  at least aln_long_workspace_size(...) bytes, 256-byte aligned: two bottom-row
+ *                         slots of (m + 1) * 8 bytes, plus, with ALN_TRACEBACK, the 4-bit predecessor
+ *                         code of every cell (about n * m / 2 bytes; the call returns ALN_E_UNSUPPORTED
+ *                         above 64 GiB of codes).
  * Exactness: 32-bit lanes; the call returns ALN_E_SCORING if the score range of an n x m problem
  * could leave +-2^28. */
 aln_status_t aln_align_long(const aln_scoring_t* scoring, const uint8_t* q, int64_t n, const uint8_t* s, int64_t m,
-                            uint32_t flags, aln_result_t* out, void* workspace, size_t workspace_bytes,
-                            hipStream_t stream);
+                            uint32_t flags, aln_result_t* out, uint32_t* cigar, int64_t cigar_capacity,
+                            void* workspace, size_t workspace_bytes, hipStream_t stream);
 
 /* Kernel timing, a profiling aid.  While enabled, every kernel the library enqueues is bracketed by
  * HIP events recorded on the same stream; aln_profile_read waits for those events and returns, per

@@ -57,7 +57,8 @@ _SIGNATURES = {
                                                  ctypes.c_uint32, ctypes.POINTER(ctypes.c_size_t)]),
     "aln_align_long": (ctypes.c_int32, [ctypes.POINTER(aln_scoring_t), ctypes.c_void_p, ctypes.c_int64,
                                         ctypes.c_void_p, ctypes.c_int64, ctypes.c_uint32, ctypes.c_void_p,
-                                        ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
+                                        ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_size_t,
+                                        ctypes.c_void_p]),
     "aln_profile_enable": (ctypes.c_int32, [ctypes.c_int]),
     "aln_profile_reset": (ctypes.c_int32, []),
     "aln_profile_read": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
@@ -151,32 +152,42 @@ def aln_long_workspace_size(scoring: Scoring, n: int, m: int, flags: int = SCORE
     return int(out.value)
 
 
-def aln_align_long(scoring: Scoring, q, n: int, s, m: int, flags: int, out, workspace, workspace_bytes: int,
-                   stream=None) -> int:
+def aln_align_long(scoring: Scoring, q, n: int, s, m: int, flags: int, out, cigar, cigar_capacity: int, workspace,
+                   workspace_bytes: int, stream=None) -> int:
     sc = scoring.c()
-    return int(lib().aln_align_long(ctypes.byref(sc), _ptr(q), n, _ptr(s), m, flags, _ptr(out), _ptr(workspace),
-                                    workspace_bytes, _stream_handle(stream)))
+    return int(lib().aln_align_long(ctypes.byref(sc), _ptr(q), n, _ptr(s), m, flags, _ptr(out), _ptr(cigar),
+                                    cigar_capacity, _ptr(workspace), workspace_bytes, _stream_handle(stream)))
 
 
 class LongAligner:
     """Owns the result and workspace buffers for aln_align_long on one device-resident pair."""
 
-    def __init__(self, scoring: Scoring, q, s, flags: int = SCORE_ONLY, device="cuda"):
+    def __init__(self, scoring: Scoring, q, s, flags: int = SCORE_ONLY, device="cuda", cigar_capacity=None):
         import torch
         self.scoring, self.q, self.s, self.flags = scoring, q, s, flags
         self.n, self.m = int(q.numel()), int(s.numel())
         self.out = torch.empty(8, dtype=torch.int32, device=device)
+        self.cigar, self.cap = None, 0
+        if flags & TRACEBACK:
+            self.cap = self.n + self.m + 1 if cigar_capacity is None else int(cigar_capacity)
+            self.cigar = torch.empty(max(self.cap, 1), dtype=torch.int32, device=device)
         self.ws_bytes = aln_long_workspace_size(scoring, self.n, self.m, flags)
         self.workspace = torch.empty(max(self.ws_bytes, 256), dtype=torch.uint8, device=device)
 
     def run(self, stream=None):
-        st = aln_align_long(self.scoring, self.q, self.n, self.s, self.m, self.flags, self.out, self.workspace,
-                            self.ws_bytes, stream)
+        st = aln_align_long(self.scoring, self.q, self.n, self.s, self.m, self.flags, self.out, self.cigar, self.cap,
+                            self.workspace, self.ws_bytes, stream)
         if st != 0:
             raise AlnError(st, "aln_align_long")
 
     def result(self):
         return self.out.to("cpu").numpy().view(RESULT_DTYPE)[0]
+
+    def cigar_runs(self):
+        r = self.result()
+        L = min(int(r["cigar_len"]), self.cap)
+        w = self.cigar[:L].to("cpu").numpy().view(np.uint32)
+        return [(int(x) >> 4, int(x) & 15) for x in w]
 
 
 class aln_profile_entry_t(ctypes.Structure):

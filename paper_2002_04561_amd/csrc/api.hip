@@ -55,9 +55,10 @@ aln_status_t make_params(const aln_scoring_t* sc, KParams* kp) {
 
 // Every exact score of an n x m problem lies in [3*go + (n+m)*ge, min(n,m)*max(sigma_max, 0)];
 // the 32-bit lanes need both ends well inside +-2^29 (the pad letter scores -2^29).
+// The wavefront engine also adds a row bias of up to n*|ge| to every value.
 static bool fits_i32(const KParams& kp, int64_t max_n, int64_t max_m) {
   const int64_t mn = max_n < max_m ? max_n : max_m;
-  const int64_t up = mn * (kp.sigma_max > 0 ? kp.sigma_max : 0);
+  const int64_t up = mn * (kp.sigma_max > 0 ? kp.sigma_max : 0) - max_n * (int64_t)kp.ge;
   const int64_t lo = 3 * (int64_t)kp.go + (max_n + max_m) * (int64_t)kp.ge;
   const int64_t lim = (int64_t)1 << 28;
   return up < lim && -lo < lim;
@@ -127,11 +128,9 @@ static aln_status_t batch_layout(const KParams& kp, int64_t n_pairs, int64_t max
   L->off_redo_cnt = off;
   off += 256;
   L->off_split = off;
-  if (!tb) {
-    st = plan_split(n_pairs, total_q, total_s, &L->sp);
-    if (st != ALN_OK) return st;
-    off += L->sp.total_bytes;
-  }
+  st = plan_split(n_pairs, tb ? 0 : total_q, tb ? 0 : total_s, !tb, &L->sp);
+  if (st != ALN_OK) return st;
+  off += L->sp.total_bytes;
   L->total = off;
   return ALN_OK;
 }
@@ -175,18 +174,17 @@ aln_status_t aln_align_batch(const aln_scoring_t* scoring, int64_t n_pairs, cons
   int* redo_idx = reinterpret_cast<int*>(base + L.off_redo);
   int* redo_cnt = reinterpret_cast<int*>(base + L.off_redo_cnt);
 
-  // which pairs the inter-sequence kernels see: all of them, or the small ones of a score-only call
-  const int* list = nullptr;
-  const int* list_cnt = nullptr;
+  // the inter-sequence kernels see a shape-sorted list: all pairs of a traceback call, the small
+  // ones of a score-only call (whose large pairs go to the wavefront engine)
+  char* split_ws = base + L.off_split;
+  launch_split(L.sp, n_pairs, q_off, s_off, max_n, max_m, split_ws, stream);
   if (!tb) {
-    char* split_ws = base + L.off_split;
-    launch_split(L.sp, n_pairs, q_off, s_off, max_n, max_m, split_ws, stream);
     WfWs W = wf_view(split_ws + L.sp.wf_base, L.sp.wf);
-    st = launch_wf_i32(kp, W, q, s, out, L.sp.wf_waves, stream);
+    st = launch_wf_i32(kp, W, q, s, out, L.sp.wf_waves, false, nullptr, 0, stream);
     if (st != ALN_OK) return st;
-    list = reinterpret_cast<const int*>(split_ws + L.sp.off_small_idx);
-    list_cnt = reinterpret_cast<const int*>(split_ws + L.sp.off_small_cnt);
   }
+  const int* list = reinterpret_cast<const int*>(split_ws + L.sp.off_small_idx);
+  const int* list_cnt = reinterpret_cast<const int*>(split_ws + L.sp.off_small_cnt);
   if (!L.use16)
     return launch_batch_i32(kp, L.bp, q, q_off, s, s_off, tb, out, cigar, cigar_off, workspace, list, list_cnt, 0u,
                             stream);
@@ -212,38 +210,44 @@ aln_status_t aln_align_batch(const aln_scoring_t* scoring, int64_t n_pairs, cons
                           ALN_RES_INT32_REDO, stream);
 }
 
+// Traceback of one long pair stores 4 bits per cell; beyond this the call is refused.
+static const int64_t kMaxLongCodeBytes = (int64_t)64 << 30;
+
 aln_status_t aln_long_workspace_size(const aln_scoring_t* scoring, int64_t n, int64_t m, uint32_t flags,
                                      size_t* bytes) {
   if (!bytes || n < 0 || m < 0 || n >= (1ll << 31) || m >= (1ll << 31)) return ALN_E_INVALID;
   if (flags & ~(ALN_TRACEBACK | ALN_FORCE_INT32 | ALN_FORCE_INT16)) return ALN_E_INVALID;
-  if (flags & ALN_TRACEBACK) return ALN_E_UNSUPPORTED;
+  const bool tb = (flags & ALN_TRACEBACK) != 0;
+  if (tb && (n + kWfBand) / 2 * m > kMaxLongCodeBytes) return ALN_E_UNSUPPORTED;
   KParams kp;
   aln_status_t st = make_params(scoring, &kp);
   if (st != ALN_OK) return st;
   if (!fits_i32(kp, n, m)) return ALN_E_SCORING;
   LongPlan pl;
-  st = plan_long(n, m, &pl);
+  st = plan_long(n, m, tb, &pl);
   if (st != ALN_OK) return st;
   *bytes = pl.total_bytes;
   return ALN_OK;
 }
 
 aln_status_t aln_align_long(const aln_scoring_t* scoring, const uint8_t* q, int64_t n, const uint8_t* s, int64_t m,
-                            uint32_t flags, aln_result_t* out, void* workspace, size_t workspace_bytes,
-                            hipStream_t stream) {
+                            uint32_t flags, aln_result_t* out, uint32_t* cigar, int64_t cigar_capacity,
+                            void* workspace, size_t workspace_bytes, hipStream_t stream) {
   if (n < 0 || m < 0 || n >= (1ll << 31) || m >= (1ll << 31) || !out) return ALN_E_INVALID;
   if ((n > 0 && !q) || (m > 0 && !s)) return ALN_E_INVALID;
   if (flags & ~(ALN_TRACEBACK | ALN_FORCE_INT32 | ALN_FORCE_INT16)) return ALN_E_INVALID;
-  if (flags & ALN_TRACEBACK) return ALN_E_UNSUPPORTED;
+  const bool tb = (flags & ALN_TRACEBACK) != 0;
+  if (tb && (!cigar || cigar_capacity < 0)) return ALN_E_INVALID;
+  if (tb && (n + kWfBand) / 2 * m > kMaxLongCodeBytes) return ALN_E_UNSUPPORTED;
   KParams kp;
   aln_status_t st = make_params(scoring, &kp);
   if (st != ALN_OK) return st;
   if (!fits_i32(kp, n, m)) return ALN_E_SCORING;
   LongPlan pl;
-  st = plan_long(n, m, &pl);
+  st = plan_long(n, m, tb, &pl);
   if (st != ALN_OK) return st;
   if (!workspace || workspace_bytes < pl.total_bytes) return ALN_E_WORKSPACE;
-  return launch_long(kp, pl, q, n, s, m, out, workspace, stream);
+  return launch_long(kp, pl, q, n, s, m, out, cigar, tb ? cigar_capacity : 0, workspace, stream);
 }
 
 }  // extern "C"

@@ -183,8 +183,10 @@ __global__ __launch_bounds__(kI16Block) void batch_i16_kernel(
       const int rnA = nn[0] - 1 - i0, rnB = nn[1] - 1 - i0;
       const bool lastA = rnA >= 0 && rnA < R, lastB = rnB >= 0 && rnB < R;
       const bool track_last = (MODE == ALN_SEMIGLOBAL) && __any(lastA || lastB);
-      for (int j = 1; j <= mmax; ++j) {
-        int ca = P.alphabet, cb = P.alphabet;  // pad letter of the profile
+      // Letters and top-row inputs of column j (the pad letter of the profile past a subject's end).
+      auto fetch = [&](int j, int& ca, int& cb, uint2& top) {
+        ca = P.alphabet;
+        cb = P.alphabet;
         if (j <= mm[0]) {
           const int c = s[sb[0] + j - 1];
           if (c < P.alphabet)
@@ -199,15 +201,14 @@ __global__ __launch_bounds__(kI16Block) void batch_i16_kernel(
           else
             bad[1] = true;
         }
-        s2 hup, eup;
-        if (k == 0) {
-          hup = sp((MODE == ALN_GLOBAL) ? P.go + j * P.ge : 0);
-          eup = neg2;
-        } else {
-          const uint2 v = rowbuf[(size_t)j * 64 + lane];
-          hup = from_bits(v.x);
-          eup = from_bits(v.y);
-        }
+        if (k == 0)
+          top = make_uint2(bits(sp((MODE == ALN_GLOBAL) ? P.go + j * P.ge : 0)), bits(neg2));
+        else
+          top = (j <= mmax) ? rowbuf[(size_t)j * 64 + lane] : make_uint2(0u, 0u);
+      };
+      // One column of the strip for both pairs.
+      auto column = [&](int j, int ca, int cb, uint2 top) {
+        s2 hup = from_bits(top.x), eup = from_bits(top.y);
         s2 hd = hdiag;
         hdiag = hup;
         const uint32_t* pa = reinterpret_cast<const uint32_t*>(profA + ca * R);
@@ -282,6 +283,27 @@ __global__ __launch_bounds__(kI16Block) void batch_i16_kernel(
 #pragma unroll
           for (int w = 0; w < RW; ++w)
             dirs[(((size_t)k * RW + w) * (size_t)max_m + (size_t)(j - 1)) * 64 + lane] = acc[w];
+        }
+      };
+      // Software pipeline over groups of 4 columns: the next group's global loads are issued
+      // before the current group is relaxed, so their latency hides behind the arithmetic.
+      int ca[4], cb[4];
+      uint2 top[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) fetch(1 + u, ca[u], cb[u], top[u]);
+      for (int j0 = 1; j0 <= mmax; j0 += 4) {
+        int nca[4], ncb[4];
+        uint2 ntop[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) fetch(j0 + 4 + u, nca[u], ncb[u], ntop[u]);
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (j0 + u <= mmax) column(j0 + u, ca[u], cb[u], top[u]);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          ca[u] = nca[u];
+          cb[u] = ncb[u];
+          top[u] = ntop[u];
         }
       }
       // merge this strip's rows in row order

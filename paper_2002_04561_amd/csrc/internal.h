@@ -62,6 +62,7 @@ struct WfPair {
   int32_t out_idx;       // index of the pair's aln_result_t
   int64_t item0;         // global index of the pair's first band
   int64_t row_off;       // offset (int2 units) of the pair's two bottom-row slots, 2 * (m + 1)
+  int64_t code_off;      // traceback: offset (uint16 units) of the pair's predecessor codes
 };
 
 // Device views of the wavefront engine's workspace.
@@ -74,15 +75,17 @@ struct WfWs {
   int64_t* n_items;  // total bands (device value, written by the planner)
   int* n_pairs;      // pairs in the table (device value)
   int* error;        // set when a bounded wait gives up
+  uint16_t* codes;   // traceback: [band][lane][column] codes of 4 rows (4 bits each)
 };
 
 struct WfOffsets {
-  size_t pairs, rows, flags, res, misc;
+  size_t pairs, rows, flags, res, misc, codes;
 };
 
 struct LongPlan {
   int64_t nb;
   int n_waves;
+  bool tb;
   WfOffsets off;
   size_t total_bytes;
 };
@@ -130,22 +133,23 @@ aln_status_t launch_batch_i16(const KParams& kp, const BatchPlan16& plan, const 
 
 // wf_i32.hip
 int wf_waves();
-size_t wf_layout(int64_t max_pairs, int64_t max_items, int64_t row_words, WfOffsets* o);
+size_t wf_layout(int64_t max_pairs, int64_t max_items, int64_t row_words, int64_t code_words, WfOffsets* o);
 WfWs wf_view(void* base, const WfOffsets& o);
 aln_status_t launch_wf_i32(const KParams& kp, const WfWs& W, const uint8_t* q, const uint8_t* s, aln_result_t* out,
-                           int max_waves, hipStream_t stream);
-aln_status_t plan_long(int64_t n, int64_t m, LongPlan* plan);
+                           int max_waves, bool tb, uint32_t* cigar, int64_t cigar_cap, hipStream_t stream);
+aln_status_t plan_long(int64_t n, int64_t m, bool tb, LongPlan* plan);
 aln_status_t launch_long(const KParams& kp, const LongPlan& plan, const uint8_t* q, int64_t n, const uint8_t* s,
-                         int64_t m, aln_result_t* out, void* ws, hipStream_t stream);
+                         int64_t m, aln_result_t* out, uint32_t* cigar, int64_t cigar_cap, void* ws,
+                         hipStream_t stream);
 
 // batch_plan.hip
 struct SplitPlan {
   int64_t big_cells;  // pairs with n*m >= big_cells go to the wavefront engine
   WfOffsets wf;
-  size_t off_small_idx, off_small_cnt, wf_base, total_bytes;
+  size_t off_small_idx, off_small_cnt, off_keys, off_hist, wf_base, total_bytes;
   int wf_waves;
 };
-aln_status_t plan_split(int64_t n_pairs, int64_t total_q, int64_t total_s, SplitPlan* sp);
+aln_status_t plan_split(int64_t n_pairs, int64_t total_q, int64_t total_s, bool route_big, SplitPlan* sp);
 void launch_split(const SplitPlan& sp, int64_t n_pairs, const int64_t* q_off, const int64_t* s_off, int64_t max_n,
                   int64_t max_m, void* ws, hipStream_t stream);
 

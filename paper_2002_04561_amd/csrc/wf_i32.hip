@@ -12,7 +12,8 @@
 // several pairs of different sizes share the device the way the paper's
 // dynamic wavefront shares its queue between alignments (Sec. IV-A).  A band's
 // bottom row goes to one of two row slots of its pair in HBM; a per-item
-// progress counter, published with release semantics, tells the next band how
+// progress counter, stored after the row data has completed (all cross-wave
+// data and flags use device-coherent sc1 accesses), tells the next band how
 // many columns are ready (the tile border publication of Sec. IV-B, with flags
 // instead of one kernel launch per tile diagonal).  Two slots suffice: band
 // b+2 can only write column c after band b+1 has consumed column c of the
@@ -20,15 +21,18 @@
 // b, so every wait is on a band that is already running; every wait is also
 // bounded -- a wave that spins too long raises an error flag and leaves, so
 // the grid always drains.
+#include <type_traits>
+
 #include "internal.h"
+#include "walk.h"
 
 namespace mialign {
 namespace {
 
 constexpr int kWfWavesPerBlock = 4;
 constexpr int kWfBlock = 64 * kWfWavesPerBlock;
-constexpr int kWfWavesPerCU = 4;
-constexpr long long kSpinLimit = 1ll << 25;
+constexpr int kWfWavesPerCU = 8;
+constexpr long long kSpinLimit = 1ll << 22;
 
 __device__ __forceinline__ int dpp_shr1(int old, int src) {
   return __builtin_amdgcn_update_dpp(old, src, 0x138, 0xf, 0xf, false);  // wave_shr:1, lane 0 keeps old
@@ -42,19 +46,29 @@ __device__ __forceinline__ bool better(int s1, int i1, int j1, int s2, int i2, i
   return s1 > s2 || (s1 == s2 && (i1 < i2 || (i1 == i2 && j1 < j2)));
 }
 
-template <int MODE, bool AFFINE, bool SMALL, int R>
+// Values are kept with a row bias: Hb(i,j) = H(i,j) - i*ge, and likewise E and F.  Then
+//   Eb(i,j) = max(Eb(i-1,j), Hb(i-1,j) + go)          (extension costs nothing: one add less)
+//   Fb(i,j) = max(Fb(i,j-1) + ge, Hb(i,j-1) + go + ge)
+//   Hb(i,j) = max(Hb(i-1,j-1) + sigma - ge, Eb, Fb [, -i*ge for local])
+// which is Eqs. (1), (4), (5) with every term shifted by the same per-row constant.
+template <int MODE, bool AFFINE, bool SMALL, bool TB, int R>
 __global__ __launch_bounds__(kWfBlock) void wf_i32_kernel(const KParams P, const uint8_t* __restrict__ Q,
                                                           const uint8_t* __restrict__ S, WfWs W) {
-  __shared__ int32_t tab[kTab * kTab];
+  __shared__ int32_t tab[SMALL ? 1 : kTab * kTab];
+  __shared__ int4 stage[kWfWavesPerBlock][3][16];  // lane-0 inputs of 64 steps: H, E, letter
   if (!SMALL) {
     for (int k = threadIdx.x; k < kTab * kTab; k += blockDim.x) {
       const int a = k / kTab, b = k % kTab;
-      tab[k] = (a >= P.alphabet || b >= P.alphabet) ? -kBig32 : (int32_t)P.sig[a * kMaxAlphabet + b];
+      tab[k] = (a >= P.alphabet || b >= P.alphabet) ? -kBig32 : (int32_t)P.sig[a * kMaxAlphabet + b] - P.ge;
     }
     __syncthreads();
   }
   constexpr int BH = 64 * R;
   const int lane = threadIdx.x & 63;
+  const int wib = threadIdx.x >> 6;
+  int* st_h = reinterpret_cast<int*>(&stage[wib][0][0]);
+  int* st_e = reinterpret_cast<int*>(&stage[wib][1][0]);
+  int* st_c = reinterpret_cast<int*>(&stage[wib][2][0]);
   const int32_t go = P.go, ge = P.ge, goe = P.goe;
   const int np = *W.n_pairs;
   const int64_t n_items = *W.n_items;
@@ -82,8 +96,8 @@ __global__ __launch_bounds__(kWfBlock) void wf_i32_kernel(const KParams P, const
     const int64_t ld = (int64_t)m + 1;
 
     const int i0 = b * BH;
-    int prof[R];  // SMALL: 4 bytes sigma(q_i, a); else: q_i * kTab
-    int32_t hl[R], f[R], bv[R];
+    int prof[R];  // SMALL: 4 bytes sigma(q_i, a) - ge; else: q_i * kTab
+    int32_t hl[R], f[R], bv[R], nu[R];
     int bj[R];
     bool bad = false;
 #pragma unroll
@@ -100,24 +114,26 @@ __global__ __launch_bounds__(kWfBlock) void wf_i32_kernel(const KParams P, const
       if (SMALL) {
         uint32_t w = 0;
         for (int a = 0; a < 4; ++a) {
-          const int v = (c < P.alphabet && a < P.alphabet) ? (int)P.sig[c * kMaxAlphabet + a] : -128;
+          const int v = (c < P.alphabet && a < P.alphabet) ? (int)P.sig[c * kMaxAlphabet + a] - ge : -128;
           w |= ((uint32_t)(v & 0xff)) << (8 * a);
         }
         prof[r] = (int)w;
       } else {
         prof[r] = c * kTab;
       }
-      hl[r] = (MODE == ALN_GLOBAL) ? go + i * ge : 0;
+      hl[r] = (MODE == ALN_GLOBAL) ? go : -i * ge;  // Hb(i, 0)
       f[r] = kNeg32;
+      nu[r] = -i * ge;                                // local floor: H = 0
       bv[r] = kNeg32;
       bj[r] = 0;
     }
     const int irow0 = i0 + lane * R;  // the row just above this lane's first row
-    int32_t diag = (MODE == ALN_GLOBAL && irow0 > 0) ? go + irow0 * ge : 0;
+    int32_t diag = (MODE == ALN_GLOBAL) ? (irow0 > 0 ? go : 0) : -irow0 * ge;  // Hb(irow0, 0)
+    uint16_t* __restrict__ codes = TB ? W.codes + pr.code_off + (size_t)(b * 64 + lane) * (size_t)m : nullptr;
     int32_t bot_h = 0, bot_e = kNeg32, cur_c = 0, out_h = 0, out_e = 0;
     // semi-global: the band holding row n tracks row n's running maximum
     const bool last_band = (b == nb - 1);
-    int32_t brow = 0;
+    int32_t brow = -n * ge;  // Hb(n, 0), i.e. H(n, 0) = 0
     int browj = 0;
     const int rn = n - 1 - irow0;  // index of row n among this lane's rows
 
@@ -150,13 +166,13 @@ __global__ __launch_bounds__(kWfBlock) void wf_i32_kernel(const KParams P, const
           if (lane == 0) {
             long long spins = 0;
             for (;;) {
-              v = __hip_atomic_load(W.flags + (t - 1), __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+              v = __hip_atomic_load(W.flags + (t - 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
               if (v >= need) break;
               if (++spins > kSpinLimit || __hip_atomic_load(W.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
                 v = -1;
                 break;
               }
-              __builtin_amdgcn_s_sleep(2);
+              __builtin_amdgcn_s_sleep(1);
             }
           }
           v = __shfl(v, 0, 64);
@@ -165,7 +181,9 @@ __global__ __launch_bounds__(kWfBlock) void wf_i32_kernel(const KParams P, const
             failed = true;
             break;
           }
-          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+          // The row data below is read with device-coherent (sc1) loads issued after the flag load has
+          // returned, so they observe the producer's sc1 stores that completed before its flag store.
+          asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
           seen = v;
         }
         th = 0;
@@ -177,28 +195,44 @@ __global__ __launch_bounds__(kWfBlock) void wf_i32_kernel(const KParams P, const
           te = (int32_t)(pv >> 32);
         }
       }
-#pragma unroll 4
-      for (int u = 0; u < 64; ++u) {
-        const int j = tb + u - lane + 1;
-        const int in_h = dpp_shr1(__builtin_amdgcn_readlane(th, u), bot_h);
-        const int in_e = dpp_shr1(__builtin_amdgcn_readlane(te, u), bot_e);
-        const int in_c = dpp_shr1(__builtin_amdgcn_readlane(sreg, u), cur_c);
+      st_h[lane] = th;
+      st_e[lane] = te;
+      st_c[lane] = sreg;
+      // One step: lane l relaxes column j = t - l + 1 for its R rows.
+      auto step = [&](int t, int in_top_h, int in_top_e, int in_top_c, auto checked, int32_t* hk) {
+        const int j = t - lane + 1;
+        const int in_h = dpp_shr1(in_top_h, bot_h);
+        const int in_e = dpp_shr1(in_top_e, bot_e);
+        const int in_c = dpp_shr1(in_top_c, cur_c);
         cur_c = in_c;
-        if (j >= 1 && j <= m) {
+        if (!decltype(checked)::value || (j >= 1 && j <= m)) {
           int32_t hd = diag, hup = in_h, eup = in_e;
           int32_t hn = 0;
+          uint32_t word = 0;
 #pragma unroll
           for (int r = 0; r < R; ++r) {
             const int32_t hlo = hl[r];
-            const int32_t e = AFFINE ? max(eup + ge, hup + goe) : hup + ge;
+            const int32_t e = AFFINE ? max(eup, hup + go) : hup;
             const int32_t ff = AFFINE ? max(f[r] + ge, hlo + goe) : hlo + ge;
             const int32_t sg = SMALL ? __builtin_amdgcn_sbfe(prof[r], in_c, 8) : tab[prof[r] + in_c];
-            int32_t h = max(hd + sg, max(e, ff));
+            const int32_t d = hd + sg;
+            int32_t h = max(d, max(e, ff));
+            if (MODE == ALN_LOCAL) h = max(h, nu[r]);
+            if (TB) {
+              uint32_t src = (d == h) ? 0u : ((e == h) ? 1u : 2u);
+              if (MODE == ALN_LOCAL && h == nu[r]) src = 3u;
+              const uint32_t xe = AFFINE ? (uint32_t)(hup + go != e) : 0u;
+              const uint32_t xf = AFFINE ? (uint32_t)(hlo + goe != ff) : 0u;
+              word |= (src | (xe << 2) | (xf << 3)) << (4 * r);
+            }
             if (MODE == ALN_LOCAL) {
-              h = max(h, 0);
-              if (h > bv[r]) {
-                bv[r] = h;
-                bj[r] = j;
+              if (decltype(checked)::value) {
+                if (h > bv[r]) {
+                  bv[r] = h;
+                  bj[r] = j;
+                }
+              } else {
+                hk[r] = h;
               }
             }
             if (MODE == ALN_SEMIGLOBAL && r == rn) hn = h;
@@ -208,6 +242,7 @@ __global__ __launch_bounds__(kWfBlock) void wf_i32_kernel(const KParams P, const
             hup = h;
             eup = e;
           }
+          if (TB) codes[j - 1] = (uint16_t)word;
           if (MODE == ALN_SEMIGLOBAL && last_band && rn >= 0 && rn < R && hn > brow) {
             brow = hn;
             browj = j;
@@ -218,6 +253,40 @@ __global__ __launch_bounds__(kWfBlock) void wf_i32_kernel(const KParams P, const
         }
         out_h = dpp_shl1(bot_h, out_h);
         out_e = dpp_shl1(bot_e, out_e);
+      };
+      for (int g4 = 0; g4 < 16; ++g4) {
+        const int t0 = tb + 4 * g4;
+        const int4 vh = reinterpret_cast<const int4*>(st_h)[g4];
+        const int4 ve = reinterpret_cast<const int4*>(st_e)[g4];
+        const int4 vc = reinterpret_cast<const int4*>(st_c)[g4];
+        if (t0 >= 63 && t0 + 3 < m) {
+          // every lane is inside the matrix: no range test; local optima are tracked per 4 steps
+          int32_t hk[4][R];
+          step(t0, vh.x, ve.x, vc.x, std::false_type(), hk[0]);
+          step(t0 + 1, vh.y, ve.y, vc.y, std::false_type(), hk[1]);
+          step(t0 + 2, vh.z, ve.z, vc.z, std::false_type(), hk[2]);
+          step(t0 + 3, vh.w, ve.w, vc.w, std::false_type(), hk[3]);
+          if (MODE == ALN_LOCAL) {
+            bool imp = false;
+#pragma unroll
+            for (int r = 0; r < R; ++r) imp |= max(max(hk[0][r], hk[1][r]), max(hk[2][r], hk[3][r])) > bv[r];
+            if (imp) {
+#pragma unroll
+              for (int k = 0; k < 4; ++k)
+#pragma unroll
+                for (int r = 0; r < R; ++r)
+                  if (hk[k][r] > bv[r]) {
+                    bv[r] = hk[k][r];
+                    bj[r] = t0 + k - lane + 1;
+                  }
+            }
+          }
+        } else {
+          step(t0, vh.x, ve.x, vc.x, std::true_type(), nullptr);
+          step(t0 + 1, vh.y, ve.y, vc.y, std::true_type(), nullptr);
+          step(t0 + 2, vh.z, ve.z, vc.z, std::true_type(), nullptr);
+          step(t0 + 3, vh.w, ve.w, vc.w, std::true_type(), nullptr);
+        }
       }
       // lane u now holds lane 63's outputs of step tb+u, i.e. column tb+u-62
       if (b + 1 < nb) {
@@ -228,7 +297,10 @@ __global__ __launch_bounds__(kWfBlock) void wf_i32_kernel(const KParams P, const
                              __HIP_MEMORY_SCOPE_AGENT);
         }
         const int published = min(tb + 1, m);
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        // Publication: the row stores above are device-coherent (sc1) atomics; waiting for their
+        // completion before the sc1 flag store orders them without an L2 write-back (an agent-scope
+        // release fence would emit buffer_wbl2 on every publication).
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
         if (published >= 1 && lane == 0)
           __hip_atomic_store(W.flags + t, published, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
@@ -243,15 +315,15 @@ __global__ __launch_bounds__(kWfBlock) void wf_i32_kernel(const KParams P, const
       int sc = 0, jj = 0;
       bool cand = false;
       if (MODE == ALN_LOCAL) {
-        sc = bv[r];
+        sc = bv[r] + i * ge;
         jj = bj[r];
         cand = sc > 0;
       } else if (MODE == ALN_SEMIGLOBAL) {
-        sc = hl[r];  // H(i, m): last-column candidate; row n is handled below
+        sc = hl[r] + i * ge;  // H(i, m): last-column candidate; row n is handled below
         jj = m;
         cand = (i < n);
       } else {
-        sc = hl[r];
+        sc = hl[r] + i * ge;
         jj = m;
         cand = (i == n);
       }
@@ -261,10 +333,14 @@ __global__ __launch_bounds__(kWfBlock) void wf_i32_kernel(const KParams P, const
         bjj = jj;
       }
     }
-    if (MODE == ALN_SEMIGLOBAL && last_band && rn >= 0 && rn < R && better(brow, n, browj, bs, bi, bjj)) {
-      bs = brow;
-      bi = n;
-      bjj = browj;
+    if (MODE == ALN_SEMIGLOBAL && last_band && rn >= 0 && rn < R) {
+      // row n: (n, 0) with H = 0 first, then its running maximum over j in column order
+      const int rowv = (browj > 0) ? brow + n * ge : 0;
+      if (better(rowv, n, browj, bs, bi, bjj)) {
+        bs = rowv;
+        bi = n;
+        bjj = browj;
+      }
     }
     for (int o = 32; o >= 1; o >>= 1) {
       const int s2 = __shfl_xor(bs, o, 64), i2 = __shfl_xor(bi, o, 64), j2 = __shfl_xor(bjj, o, 64);
@@ -280,7 +356,9 @@ __global__ __launch_bounds__(kWfBlock) void wf_i32_kernel(const KParams P, const
 }
 
 // One wave per pair: reduces the pair's band optima into its aln_result_t.
-__global__ __launch_bounds__(256) void wf_finish_kernel(const KParams P, WfWs W, aln_result_t* __restrict__ out) {
+template <int MODE, bool TB>
+__global__ __launch_bounds__(256) void wf_finish_kernel(const KParams P, WfWs W, aln_result_t* __restrict__ out,
+                                                        uint32_t* __restrict__ cigar, int64_t cigar_cap) {
   const int lane = threadIdx.x & 63;
   const int np = *W.n_pairs;
   const bool err = __hip_atomic_load(W.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
@@ -338,6 +416,20 @@ __global__ __launch_bounds__(256) void wf_finish_kernel(const KParams P, WfWs W,
       r.q_end = 0;
       r.s_end = 0;
     }
+    if (TB && r.flags == 0) {
+      const uint16_t* __restrict__ codes = W.codes + pr.code_off;
+      auto code = [&](int ii, int jj) -> uint32_t {
+        const int bb = (ii - 1) / kWfBand, rr = (ii - 1) % kWfBand;
+        const uint32_t w = codes[((size_t)bb * 64 + (size_t)(rr / kWfR)) * (size_t)m + (size_t)(jj - 1)];
+        return (w >> (4 * (rr % kWfR))) & 15u;
+      };
+      int qbeg, sbeg, runs;
+      walk_back<MODE>(code, r.q_end, r.s_end, cigar, cigar_cap, &qbeg, &sbeg, &runs);
+      r.q_begin = qbeg;
+      r.s_begin = sbeg;
+      r.cigar_len = runs;
+      if (runs > cigar_cap) r.flags |= ALN_RES_CIGAR_TRUNC;
+    }
     out[pr.out_idx] = r;
   }
 }
@@ -364,6 +456,7 @@ __global__ void wf_single_pair_kernel(WfWs W, int n, int m, int band_rows) {
     p.nb = (n > 0 && m > 0) ? (n + band_rows - 1) / band_rows : 0;
     p.item0 = 0;
     p.row_off = 0;
+    p.code_off = 0;
     p.out_idx = 0;
     W.pairs[0] = p;
     *W.n_pairs = 1;
@@ -371,22 +464,36 @@ __global__ void wf_single_pair_kernel(WfWs W, int n, int m, int band_rows) {
   }
 }
 
-template <int MODE, bool AFFINE, bool SMALL>
+template <int MODE, bool AFFINE, bool SMALL, bool TB>
 void launch_wf_t(const KParams& kp, const uint8_t* q, const uint8_t* s, const WfWs& W, int n_waves,
                  hipStream_t stream) {
   const int blocks = (n_waves + kWfWavesPerBlock - 1) / kWfWavesPerBlock;
-  ProfScope prof("wavefront_i32", stream);
-  hipLaunchKernelGGL((wf_i32_kernel<MODE, AFFINE, SMALL, kWfR>), dim3(blocks), dim3(kWfBlock), 0, stream, kp, q, s,
-                     W);
+  ProfScope prof(TB ? "wavefront_i32_traceback" : "wavefront_i32", stream);
+  hipLaunchKernelGGL((wf_i32_kernel<MODE, AFFINE, SMALL, TB, kWfR>), dim3(blocks), dim3(kWfBlock), 0, stream, kp,
+                     q, s, W);
+}
+
+template <int MODE, bool TB>
+void launch_wf_m(const KParams& kp, const uint8_t* q, const uint8_t* s, const WfWs& W, int nw, hipStream_t st) {
+  const bool affine = kp.go != 0;
+  // the per-row profile holds sigma - ge in a signed byte
+  const bool small = kp.alphabet <= 4 && kp.sigma_max - kp.ge <= 127 && kp.sigma_min - kp.ge >= -127;
+  if (affine && small) launch_wf_t<MODE, true, true, TB>(kp, q, s, W, nw, st);
+  if (affine && !small) launch_wf_t<MODE, true, false, TB>(kp, q, s, W, nw, st);
+  if (!affine && small) launch_wf_t<MODE, false, true, TB>(kp, q, s, W, nw, st);
+  if (!affine && !small) launch_wf_t<MODE, false, false, TB>(kp, q, s, W, nw, st);
 }
 
 template <int MODE>
-void launch_wf_m(const KParams& kp, const uint8_t* q, const uint8_t* s, const WfWs& W, int nw, hipStream_t st) {
-  const bool affine = kp.go != 0, small = kp.alphabet <= 4;
-  if (affine && small) launch_wf_t<MODE, true, true>(kp, q, s, W, nw, st);
-  if (affine && !small) launch_wf_t<MODE, true, false>(kp, q, s, W, nw, st);
-  if (!affine && small) launch_wf_t<MODE, false, true>(kp, q, s, W, nw, st);
-  if (!affine && !small) launch_wf_t<MODE, false, false>(kp, q, s, W, nw, st);
+void launch_wf_mode(const KParams& kp, const uint8_t* q, const uint8_t* s, const WfWs& W, int nw, bool tb,
+                    aln_result_t* out, uint32_t* cigar, int64_t cap, hipStream_t st) {
+  if (tb) {
+    launch_wf_m<MODE, true>(kp, q, s, W, nw, st);
+    hipLaunchKernelGGL((wf_finish_kernel<MODE, true>), dim3(256), dim3(256), 0, st, kp, W, out, cigar, cap);
+  } else {
+    launch_wf_m<MODE, false>(kp, q, s, W, nw, st);
+    hipLaunchKernelGGL((wf_finish_kernel<MODE, false>), dim3(256), dim3(256), 0, st, kp, W, out, cigar, cap);
+  }
 }
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -398,7 +505,7 @@ int wf_waves() {
   return cus > 0 ? cus * kWfWavesPerCU : -1;
 }
 
-size_t wf_layout(int64_t max_pairs, int64_t max_items, int64_t row_words, WfOffsets* o) {
+size_t wf_layout(int64_t max_pairs, int64_t max_items, int64_t row_words, int64_t code_words, WfOffsets* o) {
   size_t off = 0;
   o->pairs = off;
   off += align256((size_t)max_pairs * sizeof(WfPair));
@@ -410,6 +517,8 @@ size_t wf_layout(int64_t max_pairs, int64_t max_items, int64_t row_words, WfOffs
   off += align256((size_t)(max_items + 1) * sizeof(int4));
   o->misc = off;
   off += 256;
+  o->codes = off;
+  off += align256((size_t)code_words * sizeof(uint16_t));
   return off;
 }
 
@@ -424,32 +533,34 @@ WfWs wf_view(void* base_, const WfOffsets& o) {
   W.n_items = reinterpret_cast<int64_t*>(base + o.misc + 8);
   W.n_pairs = reinterpret_cast<int*>(base + o.misc + 16);
   W.error = reinterpret_cast<int*>(base + o.misc + 20);
+  W.codes = reinterpret_cast<uint16_t*>(base + o.codes);
   return W;
 }
 
 aln_status_t launch_wf_i32(const KParams& kp, const WfWs& W, const uint8_t* q, const uint8_t* s,
-                           aln_result_t* out, int max_waves, hipStream_t stream) {
+                           aln_result_t* out, int max_waves, bool tb, uint32_t* cigar, int64_t cigar_cap,
+                           hipStream_t stream) {
   hipLaunchKernelGGL(wf_reset_kernel, dim3(256), dim3(256), 0, stream, W);
   switch (kp.mode) {
     case ALN_GLOBAL:
-      launch_wf_m<ALN_GLOBAL>(kp, q, s, W, max_waves, stream);
+      launch_wf_mode<ALN_GLOBAL>(kp, q, s, W, max_waves, tb, out, cigar, cigar_cap, stream);
       break;
     case ALN_LOCAL:
-      launch_wf_m<ALN_LOCAL>(kp, q, s, W, max_waves, stream);
+      launch_wf_mode<ALN_LOCAL>(kp, q, s, W, max_waves, tb, out, cigar, cigar_cap, stream);
       break;
     default:
-      launch_wf_m<ALN_SEMIGLOBAL>(kp, q, s, W, max_waves, stream);
+      launch_wf_mode<ALN_SEMIGLOBAL>(kp, q, s, W, max_waves, tb, out, cigar, cigar_cap, stream);
       break;
   }
-  hipLaunchKernelGGL(wf_finish_kernel, dim3(256), dim3(256), 0, stream, kp, W, out);
   return hipGetLastError() == hipSuccess ? ALN_OK : ALN_E_DEVICE;
 }
 
 // ---------------------------------------------------------------------------------------------
 // aln_align_long: the engine on one pair.
 // ---------------------------------------------------------------------------------------------
-aln_status_t plan_long(int64_t n, int64_t m, LongPlan* pl) {
+aln_status_t plan_long(int64_t n, int64_t m, bool tb, LongPlan* pl) {
   pl->nb = (n + kWfBand - 1) / kWfBand;
+  pl->tb = tb;
   const int nw = wf_waves();
   if (nw <= 0) return ALN_E_DEVICE;
   int64_t waves = nw;
@@ -457,15 +568,17 @@ aln_status_t plan_long(int64_t n, int64_t m, LongPlan* pl) {
   if (want < waves) waves = want;
   if (waves < kWfWavesPerBlock) waves = kWfWavesPerBlock;
   pl->n_waves = (int)waves;
-  pl->total_bytes = wf_layout(1, pl->nb, 2 * (m + 1), &pl->off);
+  const int64_t code_words = tb ? pl->nb * 64 * m : 0;
+  pl->total_bytes = wf_layout(1, pl->nb, 2 * (m + 1), code_words, &pl->off);
   return ALN_OK;
 }
 
 aln_status_t launch_long(const KParams& kp, const LongPlan& pl, const uint8_t* q, int64_t n, const uint8_t* s,
-                         int64_t m, aln_result_t* out, void* ws, hipStream_t stream) {
+                         int64_t m, aln_result_t* out, uint32_t* cigar, int64_t cigar_cap, void* ws,
+                         hipStream_t stream) {
   WfWs W = wf_view(ws, pl.off);
   hipLaunchKernelGGL(wf_single_pair_kernel, dim3(1), dim3(64), 0, stream, W, (int)n, (int)m, kWfBand);
-  return launch_wf_i32(kp, W, q, s, out, pl.n_waves, stream);
+  return launch_wf_i32(kp, W, q, s, out, pl.n_waves, pl.tb, cigar, cigar_cap, stream);
 }
 
 }  // namespace mialign

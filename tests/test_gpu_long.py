@@ -96,3 +96,64 @@ def test_long_full_262144(gpu):
     a, b = w.pair(0)
     got = _run(a, b, 1, 4, -3, -1, 2, -3)
     assert got[:3] == (g["score"], g["q_end"], g["s_end"])
+
+
+def _run_tb(q, s, mode, A, go, ge, match=None, mismatch=None, subst=None, cap=None):
+    import torch
+
+    import paper_2002_04561_amd as aln
+    sc = aln.Scoring(mode, A, go, ge, match=match or 0, mismatch=mismatch or 0, subst=subst)
+    qd = torch.from_numpy(np.ascontiguousarray(q, dtype=np.uint8) if len(q) else np.zeros(1, np.uint8)).cuda()
+    sd = torch.from_numpy(np.ascontiguousarray(s, dtype=np.uint8) if len(s) else np.zeros(1, np.uint8)).cuda()
+    la = aln.LongAligner(sc, qd[:len(q)], sd[:len(s)], flags=aln.TRACEBACK, cigar_capacity=cap)
+    la.run()
+    torch.cuda.synchronize()
+    r = la.result()
+    return (int(r["score"]), int(r["q_begin"]), int(r["q_end"]), int(r["s_begin"]), int(r["s_end"]),
+            la.cigar_runs(), int(r["flags"]), int(r["cigar_len"]))
+
+
+@pytest.mark.parametrize("mode", [0, 1, 2], ids=["global", "local", "semi"])
+@pytest.mark.parametrize("gap", [(0, -1), (-3, -1)], ids=["linear", "affine"])
+def test_long_traceback_shapes(gpu, mode, gap):
+    rng = np.random.default_rng(60 + mode)
+    go, ge = gap
+    sc = oracle.Scoring.simple(mode, 4, 2, -3, go, ge)
+    for (n, m) in [(1, 1), (5, 3), (64, 70), (255, 300), (257, 257), (700, 64), (1000, 1100)]:
+        q = rng.integers(0, 4, n, dtype=np.uint8)
+        s = synth.mutate_geometric(rng, q, 0.08, 0.02, 3.0)[:m]
+        if len(s) < m:
+            s = np.concatenate([s, rng.integers(0, 4, m - len(s), dtype=np.uint8)])
+        got = _run_tb(q, s, mode, 4, go, ge, match=2, mismatch=-3)
+        r = oracle.align(sc, q, s, traceback=True)
+        assert got[:6] == (r.score, r.q_begin, r.q_end, r.s_begin, r.s_end, r.cigar), (n, m)
+
+
+def test_long_traceback_protein(gpu):
+    rng = np.random.default_rng(61)
+    sig = synth.protein_sigma(rng)
+    for mode in (0, 1, 2):
+        sc = oracle.Scoring.matrix(mode, sig.astype(np.int32), -11, -1)
+        q = rng.integers(0, 20, 600, dtype=np.uint8)
+        s = rng.integers(0, 20, 520, dtype=np.uint8)
+        got = _run_tb(q, s, mode, 20, -11, -1, subst=sig)
+        r = oracle.align(sc, q, s, traceback=True)
+        assert got[:6] == (r.score, r.q_begin, r.q_end, r.s_begin, r.s_end, r.cigar), mode
+
+
+def test_long_traceback_global_1k_golden(gpu):
+    """The 1000 x 1000 global linear pair (+2/-1, gap -1) against the stored oracle CIGAR."""
+    g = json.load(open(os.path.join(HERE, "golden", "global_1k.json")))
+    w = synth.long_dna_global_1k(seed=1)
+    a, b = w.pair(0)
+    got = _run_tb(a, b, 0, 4, 0, -1, match=2, mismatch=-1)
+    assert got[0] == g["score"] and oracle.cigar_string(got[5]) == g["cigar"]
+
+
+def test_long_traceback_truncation(gpu):
+    rng = np.random.default_rng(62)
+    q = rng.integers(0, 4, 300, dtype=np.uint8)
+    s = rng.integers(0, 4, 300, dtype=np.uint8)
+    full = _run_tb(q, s, 0, 4, -3, -1, 2, -3)
+    short = _run_tb(q, s, 0, 4, -3, -1, 2, -3, cap=2)
+    assert full[7] > 2 and short[6] & 2 and short[7] == full[7]
