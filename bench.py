@@ -52,6 +52,29 @@ def make_workload(name, pairs=None):
     raise SystemExit("unknown workload %s" % name)
 
 
+def _measured_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` on `workload` from a committed PMC summary, or None.
+
+    profiles/traffic_*.json hold FETCH_SIZE / WRITE_SIZE per dispatch scaled by what the same counters
+    read for a copy of known size; a summary counts only while the kernel's source file still has the
+    hash it was taken at."""
+    import glob
+    import hashlib
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "traffic_*.json"))):
+        with open(path) as fh:
+            rec = json.load(fh)
+        if rec.get("kernel") != kernel or rec.get("workload") != workload:
+            continue
+        src = os.path.join(ROOT, rec["source"])
+        if not os.path.exists(src):
+            continue
+        with open(src, "rb") as fh:
+            digest = hashlib.sha256(fh.read()).hexdigest()[:16]
+        if digest == rec.get("source_sha256_16"):
+            return float(rec["traffic_bytes_per_launch"])
+    return None
+
+
 def _oracle_scoring(w):
     import oracle
     return oracle.Scoring.matrix(w.mode, w.sigma_table(), w.gap_open, w.gap_extend)
@@ -125,6 +148,74 @@ def spot_check(w, res, cigars, idx):
     return "bit-exact on %d sampled pairs" % len(idx)
 
 
+def time_graph(ba, stream, steps):
+    """The batch call captured once in a HIP graph and replayed `steps` times; ms per replay."""
+    import torch
+    g = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(stream)
+    with torch.cuda.stream(side):
+        with torch.cuda.graph(g):
+            ba.run()
+    stream.wait_stream(side)
+    torch.cuda.synchronize()
+    with torch.cuda.stream(stream):
+        g.replay()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            g.replay()
+        torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3 / steps, g
+
+
+def _sub_aligner(w, idx, flags, config=None):
+    import paper_2002_04561_amd as aln
+    sub = w.subset(np.asarray(idx))
+    n, m = sub.lengths()
+    q, qo, s, so = aln.to_device(sub)
+    return aln.BatchAligner(aln.scoring_of(sub), q, qo, s, so, max(int(n.max()), 1), max(int(m.max()), 1), flags,
+                            config=config), sub
+
+
+def time_per_bin(w, flags, stream, steps, config=None):
+    """One aln_align_batch call per length bin (bins of log2 max(n, m)), run back to back on one stream."""
+    import torch
+    n, m = w.lengths()
+    key = np.log2(np.maximum(np.maximum(n, m), 1)).astype(int)
+    calls = [_sub_aligner(w, np.nonzero(key == b)[0], flags, config)[0] for b in np.unique(key)]
+    for ba in calls:
+        ba.run(stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        for ba in calls:
+            ba.run(stream)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3 / steps, len(calls)
+
+
+def time_plain(w, flags, stream, count, seed=1):
+    """One pair per call: a random sample of pairs, each aligned by its own aln_align_batch call (each call
+    waits for the previous); GCUPS = sample cells / summed time."""
+    import torch
+    rng = np.random.default_rng(seed)
+    idx = np.sort(rng.choice(w.n_pairs, size=min(count, w.n_pairs), replace=False))
+    n, m = w.lengths()
+    calls = [_sub_aligner(w, [k], flags)[0] for k in idx]
+    for ba in calls[:4]:
+        ba.run(stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for ba in calls:
+        ba.run(stream)
+        stream.synchronize()
+    dt = time.perf_counter() - t0
+    cells = float(np.sum(n[idx].astype(np.int64) * m[idx]))
+    return {"gcups": round(cells / dt / 1e9, 2), "pairs": len(idx), "cells": cells, "seconds": round(dt, 4),
+            "sample": "%d random pairs, one aln_align_batch call per pair, synchronised" % len(idx)}
+
+
 def serve_stream(n_req, rate_hz, seed=5, long_len=65536):
     """The request mix of the serving workload; arrivals are Poisson at rate_hz."""
     import synth
@@ -192,6 +283,9 @@ def main():
                     help="run only a plain 1 GiB device-to-device copy (scale for rocprofv3 FETCH_SIZE/WRITE_SIZE)")
     ap.add_argument("--pairs", type=int, default=None, help="override the pair count of a batch workload")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="batch workloads: library defaults instead of autotuning")
+    ap.add_argument("--no-compare", action="store_true",
+                    help="batch workloads: skip the graph / per-length-bin / one-pair-per-call comparisons")
     ap.add_argument("--no-check", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -236,6 +330,13 @@ def main():
             ba = aln.BatchAligner(aln.scoring_of(w), q, qo, s, so, int(n.max()), int(m.max()), flags)
     torch.cuda.synchronize()
     log("device buffers ready; workspace %.3g GB" % (ba.ws_bytes / 1e9))
+    tuned = None
+    if not long_path and not args.no_tune:
+        from paper_2002_04561_amd import tune
+        t0 = time.perf_counter()
+        cfg, table = tune.tune(ba, stream, log=log)
+        tuned = {"config": cfg.__dict__, "seconds": round(time.perf_counter() - t0, 2), "candidates": len(table)}
+        log("tuned config %s in %.1f s" % (cfg, tuned["seconds"]))
     for _ in range(args.warmup):
         ba.run(stream)
     torch.cuda.synchronize()
@@ -274,7 +375,7 @@ def main():
         cells_per_launch = cells / max(launches_per_step, 1e-9)
         achieved = opc * cells_per_launch / (per_launch_ms * 1e-3) / 1e12
         roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 2), "unit": "Tops/s",
-                "frac": round(achieved / peak, 4), "traffic": None, "kernel": dom[0],
+                "frac": round(achieved / peak, 4), "traffic": _measured_traffic(dom[0], w.name), "kernel": dom[0],
                 "kernel_ms": round(per_launch_ms, 4), "ops_per_cell": opc,
                 "kernels_ms_per_step": {k: round(v[1] / args.steps, 4) for k, v in prof.items()}}
     out = {
@@ -287,6 +388,19 @@ def main():
         "parity": check,
         "roofline": roof,
     }
+    if tuned:
+        out["tuned"] = tuned
+    if not long_path and not args.no_compare:
+        gms, _ = time_graph(ba, stream, args.steps)
+        out["graph"] = {"ms_per_step": round(gms, 4), "gcups": round(cells / (gms * 1e-3) / 1e9, 2),
+                        "what": "the same call captured once in a HIP graph, replayed"}
+        log("graph replay: %.3f ms" % gms)
+        bms, nbins = time_per_bin(w, flags, stream, max(1, min(args.steps, 3)), ba.config)
+        out["per_length_bin"] = {"ms_per_step": round(bms, 4), "gcups": round(cells / (bms * 1e-3) / 1e9, 2),
+                                 "calls": nbins, "what": "one call per bin of log2 max(n, m), back to back"}
+        log("per length bin: %.3f ms in %d calls" % (bms, nbins))
+        out["plain"] = time_plain(w, flags, stream, 256 if w.name == "protein_uneven" else 2048)
+        log("plain: %s" % out["plain"])
     if not args.no_cpu_baseline:
         log("timing the oracle on a host sample ...")
         out["cpu_baseline"] = run_cpu_baseline(w)

@@ -113,8 +113,9 @@ aln_status_t aln_batch_workspace_size(const aln_scoring_t* scoring, int64_t n_pa
 
 /* Aligns n_pairs independent pairs.  Small pairs run one pair per lane (inter-sequence parallelism,
  * Sec. VI); in score-only calls, pairs with n*m >= 2^20 run on the band wavefront of aln_align_long
- * instead, all of them sharing one device-wide work queue (the dynamic wavefront of Sec. IV-A).  The
- * routing is decided on the device, so the host needs no copy of the lengths.
+ * instead, all of them sharing one device-wide work queue (the dynamic wavefront of Sec. IV-A),
+ * largest first.  The routing is decided on the device, so the host needs no copy of the lengths;
+ * aln_align_batch_ex sets the threshold and the other execution choices.
  *   q, s          DEVICE  concatenated uint8 codes of all queries / subjects
  *   q_off, s_off  DEVICE  int64[n_pairs+1]; pair k is q[q_off[k]:q_off[k+1]] vs s[s_off[k]:s_off[k+1]]
  *   max_n, max_m  upper bounds of the lengths (pairs above them get ALN_RES_TOO_LONG)
@@ -130,6 +131,34 @@ aln_status_t aln_align_batch(const aln_scoring_t* scoring, int64_t n_pairs, cons
                              const uint8_t* s, const int64_t* s_off, int64_t max_n, int64_t max_m, int64_t total_q,
                              int64_t total_s, uint32_t flags, aln_result_t* out, uint32_t* cigar,
                              const int64_t* cigar_off, void* workspace, size_t workspace_bytes, hipStream_t stream);
+
+/* Execution choices of a batch call.  None of them changes any result, only how the work is laid
+ * out on the device; an autotuner (paper_2002_04561_amd/tune.py) searches them per workload.  A
+ * zero field selects the default.
+ *   wf_min_cells     score-only calls: pairs with n*m >= wf_min_cells run on the band wavefront
+ *                    engine, the others one pair per lane.  0 => 2^20; negative => no pair.
+ *   wf_waves_per_cu  persistent waves per compute unit of the wavefront engine, 1..16; 0 => 8.
+ *   wf_orient        score-only calls: 1 => a wavefront pair runs with its longer sequence along
+ *                    the band rows (the transposed problem has the same optimum; ties are still
+ *                    resolved in the (i, j) order of the call); -1 => as given.  0 => 1.
+ *   small_bits       one-pair-per-lane kernels: 16 => packed 16-bit lanes where provably exact,
+ *                    with the 32-bit redo; 32 => 32-bit lanes only.  0 => 16. */
+typedef struct {
+  int64_t wf_min_cells;
+  int32_t wf_waves_per_cu;
+  int32_t wf_orient;
+  int32_t small_bits;
+  int32_t reserved[3]; /* must be zero */
+} aln_batch_config_t;
+
+/* aln_align_batch with explicit execution choices; config == NULL is aln_align_batch.  The
+ * workspace size does not depend on the config.  Returns ALN_E_INVALID for a field out of range. */
+aln_status_t aln_align_batch_ex(const aln_scoring_t* scoring, int64_t n_pairs, const uint8_t* q,
+                                const int64_t* q_off, const uint8_t* s, const int64_t* s_off, int64_t max_n,
+                                int64_t max_m, int64_t total_q, int64_t total_s, uint32_t flags,
+                                const aln_batch_config_t* config, aln_result_t* out, uint32_t* cigar,
+                                const int64_t* cigar_off, void* workspace, size_t workspace_bytes,
+                                hipStream_t stream);
 
 /* Bytes of device workspace aln_align_long needs for an n x m problem and the given flags. */
 aln_status_t aln_long_workspace_size(const aln_scoring_t* scoring, int64_t n, int64_t m, uint32_t flags,

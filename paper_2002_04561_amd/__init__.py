@@ -42,6 +42,25 @@ class aln_scoring_t(ctypes.Structure):
                 ("gap_extend", ctypes.c_int32)]
 
 
+class aln_batch_config_t(ctypes.Structure):
+    _fields_ = [("wf_min_cells", ctypes.c_int64), ("wf_waves_per_cu", ctypes.c_int32), ("wf_orient", ctypes.c_int32),
+                ("small_bits", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+
+
+@dataclass(frozen=True)
+class BatchConfig:
+    """aln_batch_config_t: execution choices of a batch call (0 = the library's default)."""
+
+    wf_min_cells: int = 0
+    wf_waves_per_cu: int = 0
+    wf_orient: int = 0
+    small_bits: int = 0
+
+    def c(self) -> aln_batch_config_t:
+        return aln_batch_config_t(self.wf_min_cells, self.wf_waves_per_cu, self.wf_orient, self.small_bits,
+                                  (ctypes.c_int32 * 3)(0, 0, 0))
+
+
 _lib = None
 
 _SIGNATURES = {
@@ -53,6 +72,11 @@ _SIGNATURES = {
                                          ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, ctypes.c_uint32,
                                          ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                          ctypes.c_size_t, ctypes.c_void_p]),
+    "aln_align_batch_ex": (ctypes.c_int32, [ctypes.POINTER(aln_scoring_t), ctypes.c_int64, ctypes.c_void_p,
+                                            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                            ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, ctypes.c_uint32,
+                                            ctypes.POINTER(aln_batch_config_t), ctypes.c_void_p, ctypes.c_void_p,
+                                            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
     "aln_long_workspace_size": (ctypes.c_int32, [ctypes.POINTER(aln_scoring_t), ctypes.c_int64, ctypes.c_int64,
                                                  ctypes.c_uint32, ctypes.POINTER(ctypes.c_size_t)]),
     "aln_align_long": (ctypes.c_int32, [ctypes.POINTER(aln_scoring_t), ctypes.c_void_p, ctypes.c_int64,
@@ -220,13 +244,25 @@ def aln_version() -> str:
     return lib().aln_version().decode()
 
 
+def aln_align_batch_ex(scoring: Scoring, n_pairs: int, q, q_off, s, s_off, max_n: int, max_m: int, total_q: int,
+                       total_s: int, flags: int, config: Optional[BatchConfig], out, cigar, cigar_off, workspace,
+                       workspace_bytes: int, stream=None) -> int:
+    """aln_align_batch with a BatchConfig (None = defaults).  Returns the status code."""
+    sc = scoring.c()
+    cfg = ctypes.byref(config.c()) if config is not None else None
+    return int(lib().aln_align_batch_ex(ctypes.byref(sc), n_pairs, _ptr(q), _ptr(q_off), _ptr(s), _ptr(s_off),
+                                        max_n, max_m, total_q, total_s, flags, cfg, _ptr(out), _ptr(cigar),
+                                        _ptr(cigar_off), _ptr(workspace), workspace_bytes, _stream_handle(stream)))
+
+
 class BatchAligner:
     """Owns the device buffers for repeated aln_align_batch calls over one set of device-resident pairs."""
 
     def __init__(self, scoring: Scoring, q, q_off, s, s_off, max_n: int, max_m: int, flags: int = SCORE_ONLY,
-                 cigar_capacity=None, device="cuda", total_q=None, total_s=None):
+                 cigar_capacity=None, device="cuda", total_q=None, total_s=None, config: Optional[BatchConfig] = None):
         import torch
         self.torch = torch
+        self.config = config
         self.scoring = scoring
         self.q, self.q_off, self.s, self.s_off = q, q_off, s, s_off
         self.n_pairs = int(q_off.numel()) - 1
@@ -252,9 +288,14 @@ class BatchAligner:
         self.workspace = torch.empty(max(self.ws_bytes, 256), dtype=torch.uint8, device=device)
 
     def run(self, stream=None):
-        st = aln_align_batch(self.scoring, self.n_pairs, self.q, self.q_off, self.s, self.s_off, self.max_n,
-                             self.max_m, self.total_q, self.total_s, self.flags, self.out, self.cigar,
-                             self.cigar_off, self.workspace, self.ws_bytes, stream)
+        if self.config is None:
+            st = aln_align_batch(self.scoring, self.n_pairs, self.q, self.q_off, self.s, self.s_off, self.max_n,
+                                 self.max_m, self.total_q, self.total_s, self.flags, self.out, self.cigar,
+                                 self.cigar_off, self.workspace, self.ws_bytes, stream)
+        else:
+            st = aln_align_batch_ex(self.scoring, self.n_pairs, self.q, self.q_off, self.s, self.s_off, self.max_n,
+                                    self.max_m, self.total_q, self.total_s, self.flags, self.config, self.out,
+                                    self.cigar, self.cigar_off, self.workspace, self.ws_bytes, stream)
         if st != 0:
             raise AlnError(st, "aln_align_batch")
 

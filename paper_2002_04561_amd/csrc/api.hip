@@ -55,10 +55,12 @@ aln_status_t make_params(const aln_scoring_t* sc, KParams* kp) {
 
 // Every exact score of an n x m problem lies in [3*go + (n+m)*ge, min(n,m)*max(sigma_max, 0)];
 // the 32-bit lanes need both ends well inside +-2^29 (the pad letter scores -2^29).
-// The wavefront engine also adds a row bias of up to n*|ge| to every value.
+// The wavefront engine also adds a row bias of up to rows*|ge| to every value, and relaxes a pair
+// transposed when that puts the longer sequence along the rows.
 static bool fits_i32(const KParams& kp, int64_t max_n, int64_t max_m) {
   const int64_t mn = max_n < max_m ? max_n : max_m;
-  const int64_t up = mn * (kp.sigma_max > 0 ? kp.sigma_max : 0) - max_n * (int64_t)kp.ge;
+  const int64_t mx = max_n < max_m ? max_m : max_n;
+  const int64_t up = mn * (kp.sigma_max > 0 ? kp.sigma_max : 0) - mx * (int64_t)kp.ge;
   const int64_t lo = 3 * (int64_t)kp.go + (max_n + max_m) * (int64_t)kp.ge;
   const int64_t lim = (int64_t)1 << 28;
   return up < lim && -lo < lim;
@@ -111,11 +113,11 @@ struct BatchLayout {
 };
 
 static aln_status_t batch_layout(const KParams& kp, int64_t n_pairs, int64_t max_n, int64_t max_m, int64_t total_q,
-                                 int64_t total_s, uint32_t flags, BatchLayout* L) {
+                                 int64_t total_s, uint32_t flags, const BatchCfg& cfg, BatchLayout* L) {
   const bool tb = (flags & ALN_TRACEBACK) != 0;
   aln_status_t st = plan_batch_i32(kp, n_pairs, max_n, max_m, tb, &L->bp);
   if (st != ALN_OK) return st;
-  L->use16 = !(flags & ALN_FORCE_INT32) && max_m < 32767;
+  L->use16 = !(flags & ALN_FORCE_INT32) && cfg.small16 && max_m < 32767;
   size_t slabs = L->bp.total_bytes;
   if (L->use16) {
     st = plan_batch_i16(kp, n_pairs, max_n, max_m, tb, &L->bp16);
@@ -128,7 +130,7 @@ static aln_status_t batch_layout(const KParams& kp, int64_t n_pairs, int64_t max
   L->off_redo_cnt = off;
   off += 256;
   L->off_split = off;
-  st = plan_split(n_pairs, tb ? 0 : total_q, tb ? 0 : total_s, !tb, &L->sp);
+  st = plan_split(n_pairs, tb ? 0 : total_q, tb ? 0 : total_s, !tb, cfg, &L->sp);
   if (st != ALN_OK) return st;
   off += L->sp.total_bytes;
   L->total = off;
@@ -143,19 +145,42 @@ aln_status_t aln_batch_workspace_size(const aln_scoring_t* scoring, int64_t n_pa
   aln_status_t st = make_params(scoring, &kp);
   if (st != ALN_OK) return st;
   if (!fits_i32(kp, max_n, max_m)) return ALN_E_SCORING;
+  // the slab sizes do not depend on the config; the 16-bit slabs are sized whenever they may be used
   BatchLayout L;
-  st = batch_layout(kp, n_pairs, max_n, max_m, total_q, total_s, flags, &L);
+  st = batch_layout(kp, n_pairs, max_n, max_m, total_q, total_s, flags, resolve_cfg(nullptr), &L);
   if (st != ALN_OK) return st;
   *bytes = L.total;
   return ALN_OK;
+}
+
+static bool cfg_valid(const aln_batch_config_t* c) {
+  if (!c) return true;
+  if (c->wf_waves_per_cu < 0 || c->wf_waves_per_cu > kWfWavesPerCUMax) return false;
+  if (c->wf_orient < -1 || c->wf_orient > 1) return false;
+  if (c->small_bits != 0 && c->small_bits != 16 && c->small_bits != 32) return false;
+  for (int k = 0; k < 3; ++k)
+    if (c->reserved[k] != 0) return false;
+  return true;
 }
 
 aln_status_t aln_align_batch(const aln_scoring_t* scoring, int64_t n_pairs, const uint8_t* q, const int64_t* q_off,
                              const uint8_t* s, const int64_t* s_off, int64_t max_n, int64_t max_m, int64_t total_q,
                              int64_t total_s, uint32_t flags, aln_result_t* out, uint32_t* cigar,
                              const int64_t* cigar_off, void* workspace, size_t workspace_bytes, hipStream_t stream) {
+  return aln_align_batch_ex(scoring, n_pairs, q, q_off, s, s_off, max_n, max_m, total_q, total_s, flags, nullptr,
+                            out, cigar, cigar_off, workspace, workspace_bytes, stream);
+}
+
+aln_status_t aln_align_batch_ex(const aln_scoring_t* scoring, int64_t n_pairs, const uint8_t* q,
+                                const int64_t* q_off, const uint8_t* s, const int64_t* s_off, int64_t max_n,
+                                int64_t max_m, int64_t total_q, int64_t total_s, uint32_t flags,
+                                const aln_batch_config_t* config, aln_result_t* out, uint32_t* cigar,
+                                const int64_t* cigar_off, void* workspace, size_t workspace_bytes,
+                                hipStream_t stream) {
   if (n_pairs < 0 || max_n < 0 || max_m < 0 || total_q < 0 || total_s < 0) return ALN_E_INVALID;
   if (flags & ~(ALN_TRACEBACK | ALN_FORCE_INT32 | ALN_FORCE_INT16)) return ALN_E_INVALID;
+  if (!cfg_valid(config)) return ALN_E_INVALID;
+  const BatchCfg cfg = resolve_cfg(config);
   KParams kp;
   aln_status_t st = make_params(scoring, &kp);
   if (st != ALN_OK) return st;
@@ -167,7 +192,7 @@ aln_status_t aln_align_batch(const aln_scoring_t* scoring, int64_t n_pairs, cons
   if (tb && (!cigar || !cigar_off)) return ALN_E_INVALID;
   if (!fits_i32(kp, max_n, max_m)) return ALN_E_SCORING;
   BatchLayout L;
-  st = batch_layout(kp, n_pairs, max_n, max_m, total_q, total_s, flags, &L);
+  st = batch_layout(kp, n_pairs, max_n, max_m, total_q, total_s, flags, cfg, &L);
   if (st != ALN_OK) return st;
   if (!workspace || workspace_bytes < L.total) return ALN_E_WORKSPACE;
   char* base = static_cast<char*>(workspace);

@@ -1,31 +1,41 @@
 // Device-side planning of a batch: routes each pair to the inter-sequence kernels (one pair per
 // lane) or, when its matrix is large, to the intra-sequence wavefront engine (one band per wave),
-// and sorts the inter-sequence pairs by shape so that the 64 or 128 pairs sharing a wave have
-// similar n and m (a wave runs max n x max m steps for all of its pairs).  Shapes are binned on a
-// log scale with 8 bins per octave of n and of m; a counting sort lays the bins out from the
-// largest to the smallest, so long pairs start first.  Everything runs on the device: a batch
-// needs no host copy of its lengths and stays capturable in a HIP graph.
+// and orders both lists with one counting sort:
+//   - inter-sequence pairs by shape, so that the 64 or 128 pairs sharing a wave have similar n and
+//     m (a wave runs max n x max m steps for all of its pairs).  Shapes are binned on a log scale
+//     with 8 bins per octave of n and of m, largest first, so long pairs start first;
+//   - wavefront pairs by cell count, largest first (longest-processing-time order for the queue),
+//     each oriented with its longer sequence along the band rows when the call allows it.
+// Everything runs on the device: a batch needs no host copy of its lengths and stays capturable
+// in a HIP graph.
 #include "internal.h"
 
 namespace mialign {
 namespace {
 
-constexpr int kShapeBins = 128;                     // per dimension
-constexpr int kKeys = kShapeBins * kShapeBins;      // sort keys
+constexpr int kShapeBins = 128;                 // per dimension
+constexpr int kSmallKeys = kShapeBins * kShapeBins;
+constexpr int kBigKeys = 1024;                  // cell-count bins of wavefront pairs
+constexpr int kKeys = kSmallKeys + kBigKeys;    // sort keys; big pairs sort above every small one
+constexpr int kScanThreads = 1024;
+static_assert(kKeys % kScanThreads == 0, "keys per scan thread");
 
 struct SplitView {
   int* small_idx;  // sorted inter-sequence list
   int* counters;   // [0] small pairs, [1] big pairs
-  int* keys;       // per pair: shape key, or -1 for a big pair
+  int* keys;       // per pair: sort key
   int* hist;       // [kKeys] counts, then cursors
 };
 
-// 8 bins per octave: floor(8 * log2(x)) for x >= 8, x itself below.
-__device__ __forceinline__ int log_bin(int64_t x) {
+// 8 bins per octave: floor(8 * log2(x)) - 16 for x >= 8, x itself below.
+__device__ __forceinline__ int log_bin_wide(int64_t x) {
   if (x < 8) return (int)(x < 0 ? 0 : x);
   const int e = 63 - __builtin_clzll((unsigned long long)x);
   const int frac = (int)((x >> (e - 3)) & 7);
-  const int b = e * 8 + frac - 16;  // x = 8 gives 8
+  return e * 8 + frac - 16;  // x = 8 gives 8
+}
+__device__ __forceinline__ int log_bin(int64_t x) {
+  const int b = log_bin_wide(x);
   return b < kShapeBins ? b : kShapeBins - 1;
 }
 
@@ -36,38 +46,28 @@ __global__ void split_reset_kernel(SplitView V) {
 
 __global__ void split_classify_kernel(int64_t n_pairs, const int64_t* __restrict__ q_off,
                                       const int64_t* __restrict__ s_off, int64_t max_n, int64_t max_m,
-                                      int64_t big_cells, SplitView V, WfWs W) {
+                                      int64_t big_cells, SplitView V) {
   for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n_pairs;
        p += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t qb = q_off[p], sb = s_off[p];
-    const int64_t n = q_off[p + 1] - qb, m = s_off[p + 1] - sb;
+    const int64_t n = q_off[p + 1] - q_off[p], m = s_off[p + 1] - s_off[p];
     const bool fits = n >= 0 && m >= 0 && n <= max_n && m <= max_m;
+    int key;
     if (fits && n > 0 && m > 0 && n * m >= big_cells) {
-      const int k = atomicAdd(&V.counters[1], 1);
-      WfPair pr;
-      pr.q_off = qb;
-      pr.s_off = sb;
-      pr.n = (int32_t)n;
-      pr.m = (int32_t)m;
-      pr.nb = (int32_t)((n + kWfBand - 1) / kWfBand);
-      pr.out_idx = (int32_t)p;
-      pr.item0 = 0;
-      pr.row_off = 0;
-      pr.code_off = 0;
-      W.pairs[k] = pr;
-      V.keys[p] = -1;
+      const int b = log_bin_wide(n * m);
+      key = kSmallKeys + (b < kBigKeys ? b : kBigKeys - 1);
+      atomicAdd(&V.counters[1], 1);
     } else {
-      const int key = log_bin(n) * kShapeBins + log_bin(m);
-      V.keys[p] = key;
-      atomicAdd(&V.hist[key], 1);
+      key = log_bin(n) * kShapeBins + log_bin(m);
     }
+    V.keys[p] = key;
+    atomicAdd(&V.hist[key], 1);
   }
 }
 
-// One block: turns the key histogram into cursors, largest shapes first, and counts the list.
-__global__ __launch_bounds__(1024) void sort_scan_kernel(SplitView V) {
-  __shared__ int part[1024];
-  constexpr int per = kKeys / 1024;
+// One block: turns the key histogram into cursors, largest keys first, and counts the small list.
+__global__ __launch_bounds__(kScanThreads) void sort_scan_kernel(SplitView V) {
+  __shared__ int part[kScanThreads];
+  constexpr int per = kKeys / kScanThreads;
   int local[per];
   int sum = 0;
   // thread t owns keys kKeys-1-(t*per) ... descending
@@ -77,7 +77,7 @@ __global__ __launch_bounds__(1024) void sort_scan_kernel(SplitView V) {
   }
   part[threadIdx.x] = sum;
   __syncthreads();
-  for (int o = 1; o < 1024; o <<= 1) {
+  for (int o = 1; o < kScanThreads; o <<= 1) {
     const int a = threadIdx.x >= o ? part[threadIdx.x - o] : 0;
     __syncthreads();
     part[threadIdx.x] += a;
@@ -88,16 +88,38 @@ __global__ __launch_bounds__(1024) void sort_scan_kernel(SplitView V) {
     V.hist[kKeys - 1 - (threadIdx.x * per + k)] = run;
     run += local[k];
   }
-  if (threadIdx.x == 1023) V.counters[0] = part[1023];
+  if (threadIdx.x == kScanThreads - 1) V.counters[0] = part[kScanThreads - 1] - V.counters[1];
 }
 
-__global__ void sort_scatter_kernel(int64_t n_pairs, SplitView V) {
+// Places every pair at its sorted position: big pairs (positions 0 .. n_big-1) become entries of
+// the wavefront pair table, small ones entries of the inter-sequence list.
+__global__ void sort_scatter_kernel(int64_t n_pairs, const int64_t* __restrict__ q_off,
+                                    const int64_t* __restrict__ s_off, int orient, SplitView V, WfWs W) {
+  const int n_big = V.counters[1];
   for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n_pairs;
        p += (int64_t)gridDim.x * blockDim.x) {
     const int key = V.keys[p];
-    if (key < 0) continue;
     const int pos = atomicAdd(&V.hist[key], 1);
-    V.small_idx[pos] = (int)p;
+    if (key < kSmallKeys) {
+      V.small_idx[pos - n_big] = (int)p;
+      continue;
+    }
+    const int64_t qb = q_off[p], sb = s_off[p];
+    const int32_t n = (int32_t)(q_off[p + 1] - qb), m = (int32_t)(s_off[p + 1] - sb);
+    const bool flip = orient && m > n;
+    WfPair pr;
+    pr.q_off = flip ? sb : qb;
+    pr.s_off = flip ? qb : sb;
+    pr.n = flip ? m : n;
+    pr.m = flip ? n : m;
+    pr.nb = (pr.n + kWfBand - 1) / kWfBand;
+    pr.out_idx = (int32_t)p;
+    pr.flip = flip ? 1 : 0;
+    pr.pad_ = 0;
+    pr.item0 = 0;
+    pr.row_off = 0;
+    pr.code_off = 0;
+    W.pairs[pos] = pr;
   }
 }
 
@@ -142,8 +164,25 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 }  // namespace
 
-aln_status_t plan_split(int64_t n_pairs, int64_t total_q, int64_t total_s, bool route_big, SplitPlan* sp) {
-  sp->big_cells = route_big ? ((int64_t)1 << 20) : INT64_MAX;
+BatchCfg resolve_cfg(const aln_batch_config_t* c) {
+  BatchCfg r;
+  r.wf_min_cells = (int64_t)1 << 20;
+  r.wf_waves_per_cu = kWfWavesPerCUDefault;
+  r.orient = true;
+  r.small16 = true;
+  if (!c) return r;
+  if (c->wf_min_cells < 0) r.wf_min_cells = INT64_MAX;
+  if (c->wf_min_cells > 0) r.wf_min_cells = c->wf_min_cells;
+  if (c->wf_waves_per_cu > 0) r.wf_waves_per_cu = c->wf_waves_per_cu;
+  if (c->wf_orient < 0) r.orient = false;
+  if (c->small_bits == 32) r.small16 = false;
+  return r;
+}
+
+aln_status_t plan_split(int64_t n_pairs, int64_t total_q, int64_t total_s, bool route_big, const BatchCfg& cfg,
+                        SplitPlan* sp) {
+  sp->big_cells = route_big ? cfg.wf_min_cells : INT64_MAX;
+  sp->orient = cfg.orient ? 1 : 0;
   size_t off = 0;
   sp->off_small_idx = off;
   off += align256((size_t)(n_pairs + 1) * sizeof(int));
@@ -154,10 +193,12 @@ aln_status_t plan_split(int64_t n_pairs, int64_t total_q, int64_t total_s, bool 
   sp->off_hist = off;
   off += align256((size_t)kKeys * sizeof(int));
   sp->wf_base = off;
-  const int64_t max_items = total_q / kWfBand + n_pairs + 1;
+  // bands run along the longer side when oriented: at most (n + m) / band + 1 per pair
+  const int64_t max_items = (total_q + total_s) / kWfBand + n_pairs + 1;
+  // a pair's row slots span its columns, min(n, m) + 1 when oriented: at most m + 1 either way
   off += wf_layout(n_pairs + 1, max_items, 2 * (total_s + n_pairs), 0, &sp->wf);
   sp->total_bytes = off;
-  sp->wf_waves = wf_waves();
+  sp->wf_waves = wf_waves(cfg.wf_waves_per_cu);
   return sp->wf_waves > 0 ? ALN_OK : ALN_E_DEVICE;
 }
 
@@ -171,14 +212,14 @@ void launch_split(const SplitPlan& sp, int64_t n_pairs, const int64_t* q_off, co
   V.hist = reinterpret_cast<int*>(base + sp.off_hist);
   WfWs W = wf_view(base + sp.wf_base, sp.wf);
   ProfScope prof("plan", stream);
-  hipLaunchKernelGGL(split_reset_kernel, dim3(64), dim3(256), 0, stream, V);
+  hipLaunchKernelGGL(split_reset_kernel, dim3(68), dim3(256), 0, stream, V);
   const int64_t blocks = (n_pairs + 255) / 256;
   const dim3 grid((unsigned)(blocks < 4096 ? (blocks > 0 ? blocks : 1) : 4096));
   hipLaunchKernelGGL(split_classify_kernel, grid, dim3(256), 0, stream, n_pairs, q_off, s_off, max_n, max_m,
-                     sp.big_cells, V, W);
+                     sp.big_cells, V);
+  hipLaunchKernelGGL(sort_scan_kernel, dim3(1), dim3(kScanThreads), 0, stream, V);
+  hipLaunchKernelGGL(sort_scatter_kernel, grid, dim3(256), 0, stream, n_pairs, q_off, s_off, sp.orient, V, W);
   hipLaunchKernelGGL(split_scan_kernel, dim3(1), dim3(1024), 0, stream, V, W);
-  hipLaunchKernelGGL(sort_scan_kernel, dim3(1), dim3(1024), 0, stream, V);
-  hipLaunchKernelGGL(sort_scatter_kernel, grid, dim3(256), 0, stream, n_pairs, V);
 }
 
 }  // namespace mialign

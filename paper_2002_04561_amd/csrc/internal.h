@@ -54,12 +54,17 @@ class ProfScope {
   hipStream_t stream_;
 };
 
-// One pair handled by the wavefront engine.
+// One pair handled by the wavefront engine.  With `flip` set the problem is relaxed transposed:
+// the rows are the subject (read from the subject array at q_off) and the columns the query (from
+// the query array at s_off); n and m are then the subject and query lengths.  Scores are unchanged
+// and optima are compared in the original (i, j) order.
 struct WfPair {
-  int64_t q_off, s_off;  // offsets of the pair's codes in the concatenated q / s arrays
-  int32_t n, m;
+  int64_t q_off, s_off;  // offsets of the row / column sequence in its concatenated array
+  int32_t n, m;          // rows, columns as relaxed
   int32_t nb;            // bands of the pair
   int32_t out_idx;       // index of the pair's aln_result_t
+  int32_t flip;          // 1: rows are the subject (score-only calls)
+  int32_t pad_;
   int64_t item0;         // global index of the pair's first band
   int64_t row_off;       // offset (int2 units) of the pair's two bottom-row slots, 2 * (m + 1)
   int64_t code_off;      // traceback: offset (uint16 units) of the pair's predecessor codes
@@ -132,7 +137,9 @@ aln_status_t launch_batch_i16(const KParams& kp, const BatchPlan16& plan, const 
                               hipStream_t stream);
 
 // wf_i32.hip
-int wf_waves();
+constexpr int kWfWavesPerCUDefault = 8;
+constexpr int kWfWavesPerCUMax = 16;
+int wf_waves(int per_cu);
 size_t wf_layout(int64_t max_pairs, int64_t max_items, int64_t row_words, int64_t code_words, WfOffsets* o);
 WfWs wf_view(void* base, const WfOffsets& o);
 aln_status_t launch_wf_i32(const KParams& kp, const WfWs& W, const uint8_t* q, const uint8_t* s, aln_result_t* out,
@@ -145,11 +152,21 @@ aln_status_t launch_long(const KParams& kp, const LongPlan& plan, const uint8_t*
 // batch_plan.hip
 struct SplitPlan {
   int64_t big_cells;  // pairs with n*m >= big_cells go to the wavefront engine
+  int orient;         // wavefront pairs run with the longer sequence along the rows
   WfOffsets wf;
   size_t off_small_idx, off_small_cnt, off_keys, off_hist, wf_base, total_bytes;
   int wf_waves;
 };
-aln_status_t plan_split(int64_t n_pairs, int64_t total_q, int64_t total_s, bool route_big, SplitPlan* sp);
+// Resolved execution choices of a batch call (defaults filled in).
+struct BatchCfg {
+  int64_t wf_min_cells;
+  int wf_waves_per_cu;
+  bool orient;
+  bool small16;
+};
+BatchCfg resolve_cfg(const aln_batch_config_t* c);
+aln_status_t plan_split(int64_t n_pairs, int64_t total_q, int64_t total_s, bool route_big, const BatchCfg& cfg,
+                        SplitPlan* sp);
 void launch_split(const SplitPlan& sp, int64_t n_pairs, const int64_t* q_off, const int64_t* s_off, int64_t max_n,
                   int64_t max_m, void* ws, hipStream_t stream);
 

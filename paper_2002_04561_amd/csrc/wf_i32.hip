@@ -12,10 +12,10 @@
 // several pairs of different sizes share the device the way the paper's
 // dynamic wavefront shares its queue between alignments (Sec. IV-A).  A band's
 // bottom row goes to one of two row slots of its pair in HBM; a per-item
-// progress counter, stored after the row data has completed (all cross-wave
-// data and flags use device-coherent sc1 accesses), tells the next band how
-// many columns are ready (the tile border publication of Sec. IV-B, with flags
-// instead of one kernel launch per tile diagonal).  Two slots suffice: band
+// progress counter, stored once the row data it covers has completed (all
+// cross-wave data and counters use device-coherent sc1 accesses), tells the
+// next band how many columns are ready (the tile border publication of
+// Sec. IV-B, with counters instead of one kernel launch per tile diagonal).  Two slots suffice: band
 // b+2 can only write column c after band b+1 has consumed column c of the
 // slot, by the chain of dependencies.  Band b+1 is only handed out after band
 // b, so every wait is on a band that is already running; every wait is also
@@ -31,8 +31,16 @@ namespace {
 
 constexpr int kWfWavesPerBlock = 4;
 constexpr int kWfBlock = 64 * kWfWavesPerBlock;
-constexpr int kWfWavesPerCU = 8;
 constexpr long long kSpinLimit = 1ll << 22;
+
+// Where a band's substitution scores sigma(row letter, column letter) - ge come from:
+//   kProfTable  a 32-bit LDS table indexed by both letters (any score range);
+//   kProfReg    alphabets of up to 4 letters: one register per row holds the scores of the row's
+//               letter against the 4 letters as signed bytes, picked with a bit-field extract;
+//   kProfLane   alphabets of up to 32 letters: per letter, every lane keeps the scores of its
+//               R = 4 rows as 4 signed bytes in one LDS word, so a step reads one word.
+// The byte forms need every sigma - ge in -127..127 (-128 marks rows past the end).
+constexpr int kProfTable = 0, kProfReg = 1, kProfLane = 2;
 
 __device__ __forceinline__ int dpp_shr1(int old, int src) {
   return __builtin_amdgcn_update_dpp(old, src, 0x138, 0xf, 0xf, false);  // wave_shr:1, lane 0 keeps old
@@ -51,12 +59,14 @@ __device__ __forceinline__ bool better(int s1, int i1, int j1, int s2, int i2, i
 //   Fb(i,j) = max(Fb(i,j-1) + ge, Hb(i,j-1) + go + ge)
 //   Hb(i,j) = max(Hb(i-1,j-1) + sigma - ge, Eb, Fb [, -i*ge for local])
 // which is Eqs. (1), (4), (5) with every term shifted by the same per-row constant.
-template <int MODE, bool AFFINE, bool SMALL, bool TB, int R>
+template <int MODE, bool AFFINE, int PROF, bool TB, int R>
 __global__ __launch_bounds__(kWfBlock) void wf_i32_kernel(const KParams P, const uint8_t* __restrict__ Q,
                                                           const uint8_t* __restrict__ S, WfWs W) {
-  __shared__ int32_t tab[SMALL ? 1 : kTab * kTab];
+  static_assert(PROF != kProfLane || R == 4, "a lane profile word holds 4 rows");
+  __shared__ int32_t tab[PROF == kProfTable ? kTab * kTab : 1];
+  __shared__ uint32_t lprof[PROF == kProfLane ? kWfWavesPerBlock * kMaxAlphabet * 64 : 1];
   __shared__ int4 stage[kWfWavesPerBlock][3][16];  // lane-0 inputs of 64 steps: H, E, letter
-  if (!SMALL) {
+  if (PROF == kProfTable) {
     for (int k = threadIdx.x; k < kTab * kTab; k += blockDim.x) {
       const int a = k / kTab, b = k % kTab;
       tab[k] = (a >= P.alphabet || b >= P.alphabet) ? -kBig32 : (int32_t)P.sig[a * kMaxAlphabet + b] - P.ge;
@@ -91,14 +101,21 @@ __global__ __launch_bounds__(kWfBlock) void wf_i32_kernel(const KParams P, const
     const WfPair pr = W.pairs[lo];
     const int b = (int)(t - pr.item0);
     const int n = pr.n, m = pr.m, nb = pr.nb;
-    const uint8_t* __restrict__ q = Q + pr.q_off;
-    const uint8_t* __restrict__ s = S + pr.s_off;
+    // rows come from the query array, columns from the subject array, or the reverse when flipped
+    const bool flip = pr.flip != 0;
+    const uint8_t* __restrict__ q = (flip ? S : Q) + pr.q_off;
+    const uint8_t* __restrict__ s = (flip ? Q : S) + pr.s_off;
     const int64_t ld = (int64_t)m + 1;
+    // sigma of a (row letter, column letter) pair, in the call's (query, subject) order
+    auto sig_rc = [&](int cr, int cc) -> int {
+      return flip ? (int)P.sig[cc * kMaxAlphabet + cr] : (int)P.sig[cr * kMaxAlphabet + cc];
+    };
 
     const int i0 = b * BH;
-    int prof[R];  // SMALL: 4 bytes sigma(q_i, a) - ge; else: q_i * kTab
+    int prof[R];  // kProfReg: 4 bytes sigma - ge against letters 0..3; kProfTable: table offset of the letter
     int32_t hl[R], f[R], bv[R], nu[R];
     int bj[R];
+    int rowc[R];
     bool bad = false;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -111,21 +128,37 @@ __global__ __launch_bounds__(kWfBlock) void wf_i32_kernel(const KParams P, const
           c = kPad;
         }
       }
-      if (SMALL) {
+      rowc[r] = c;
+      if (PROF == kProfReg) {
         uint32_t w = 0;
         for (int a = 0; a < 4; ++a) {
-          const int v = (c < P.alphabet && a < P.alphabet) ? (int)P.sig[c * kMaxAlphabet + a] - ge : -128;
+          const int v = (c < P.alphabet && a < P.alphabet) ? sig_rc(c, a) - ge : -128;
           w |= ((uint32_t)(v & 0xff)) << (8 * a);
         }
         prof[r] = (int)w;
+      } else if (PROF == kProfTable) {
+        prof[r] = flip ? c : c * kTab;  // the table is indexed [query letter][subject letter]
       } else {
-        prof[r] = c * kTab;
+        prof[r] = 0;
       }
       hl[r] = (MODE == ALN_GLOBAL) ? go : -i * ge;  // Hb(i, 0)
       f[r] = kNeg32;
       nu[r] = -i * ge;                                // local floor: H = 0
       bv[r] = kNeg32;
       bj[r] = 0;
+    }
+    uint32_t* __restrict__ lp = lprof + (PROF == kProfLane ? wib * kMaxAlphabet * 64 + lane : 0);
+    if (PROF == kProfLane) {
+      // this lane's word per column letter; each lane reads only its own words, so no barrier
+      for (int a = 0; a < P.alphabet; ++a) {
+        uint32_t w = 0;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const int v = rowc[r] < P.alphabet ? sig_rc(rowc[r], a) - ge : -128;
+          w |= ((uint32_t)(v & 0xff)) << (8 * r);
+        }
+        lp[a * 64] = w;
+      }
     }
     const int irow0 = i0 + lane * R;  // the row just above this lane's first row
     int32_t diag = (MODE == ALN_GLOBAL) ? (irow0 > 0 ? go : 0) : -irow0 * ge;  // Hb(irow0, 0)
@@ -139,11 +172,13 @@ __global__ __launch_bounds__(kWfBlock) void wf_i32_kernel(const KParams P, const
 
     int2* __restrict__ prev = W.rows + pr.row_off + (int64_t)((b + 1) & 1) * ld;
     int2* __restrict__ cur = W.rows + pr.row_off + (int64_t)(b & 1) * ld;
-    int seen = 0;  // columns of the previous band known to be published
     bool failed = false;
 
+    int seen = 0;  // columns of the previous band known to be published
+    constexpr int BLK = 64;
+
     const int steps = m + 63;
-    for (int tb = 0; tb < steps; tb += 64) {
+    for (int tb = 0; tb < steps; tb += BLK) {
       // lane-0 inputs for steps tb..tb+63 (columns tb+1..tb+64)
       const int col_in = tb + 1 + lane;
       int sreg = 0;
@@ -151,16 +186,18 @@ __global__ __launch_bounds__(kWfBlock) void wf_i32_kernel(const KParams P, const
         sreg = s[col_in - 1];
         if (sreg >= P.alphabet) {
           bad = true;
-          sreg = SMALL ? 0 : kPad;
+          sreg = PROF == kProfTable ? kPad : 0;
         }
       }
-      if (SMALL) sreg *= 8;
+      if (PROF == kProfReg) sreg *= 8;
+      if (PROF == kProfLane) sreg *= 64;
+      if (PROF == kProfTable && flip) sreg *= kTab;
       int32_t th, te;
       if (b == 0) {
         th = (MODE == ALN_GLOBAL) ? go + col_in * ge : 0;
         te = kNeg32;
       } else {
-        const int need = min(tb + 64, m);
+        const int need = min(tb + BLK, m);
         if (seen < need) {
           int v = 0;
           if (lane == 0) {
@@ -209,12 +246,15 @@ __global__ __launch_bounds__(kWfBlock) void wf_i32_kernel(const KParams P, const
           int32_t hd = diag, hup = in_h, eup = in_e;
           int32_t hn = 0;
           uint32_t word = 0;
+          const int pw = PROF == kProfLane ? (int)lp[in_c] : 0;
 #pragma unroll
           for (int r = 0; r < R; ++r) {
             const int32_t hlo = hl[r];
             const int32_t e = AFFINE ? max(eup, hup + go) : hup;
             const int32_t ff = AFFINE ? max(f[r] + ge, hlo + goe) : hlo + ge;
-            const int32_t sg = SMALL ? __builtin_amdgcn_sbfe(prof[r], in_c, 8) : tab[prof[r] + in_c];
+            const int32_t sg = PROF == kProfReg    ? __builtin_amdgcn_sbfe(prof[r], in_c, 8)
+                               : PROF == kProfLane ? __builtin_amdgcn_sbfe(pw, 8 * r, 8)
+                                                   : tab[prof[r] + in_c];
             const int32_t d = hd + sg;
             int32_t h = max(d, max(e, ff));
             if (MODE == ALN_LOCAL) h = max(h, nu[r]);
@@ -254,7 +294,7 @@ __global__ __launch_bounds__(kWfBlock) void wf_i32_kernel(const KParams P, const
         out_h = dpp_shl1(bot_h, out_h);
         out_e = dpp_shl1(bot_e, out_e);
       };
-      for (int g4 = 0; g4 < 16; ++g4) {
+      for (int g4 = 0; g4 < BLK / 4; ++g4) {
         const int t0 = tb + 4 * g4;
         const int4 vh = reinterpret_cast<const int4*>(st_h)[g4];
         const int4 ve = reinterpret_cast<const int4*>(st_e)[g4];
@@ -305,7 +345,6 @@ __global__ __launch_bounds__(kWfBlock) void wf_i32_kernel(const KParams P, const
           __hip_atomic_store(W.flags + t, published, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
     }
-
     // band optimum: (score, i, j) over this lane's rows, then across the wave
     int bs = kNeg32, bi = 0, bjj = 0;
 #pragma unroll
@@ -327,19 +366,22 @@ __global__ __launch_bounds__(kWfBlock) void wf_i32_kernel(const KParams P, const
         jj = m;
         cand = (i == n);
       }
-      if (cand && better(sc, i, jj, bs, bi, bjj)) {
+      // a flipped pair's cell (i, jj) is the call's cell (jj, i)
+      const int ci = flip ? jj : i, cj = flip ? i : jj;
+      if (cand && better(sc, ci, cj, bs, bi, bjj)) {
         bs = sc;
-        bi = i;
-        bjj = jj;
+        bi = ci;
+        bjj = cj;
       }
     }
     if (MODE == ALN_SEMIGLOBAL && last_band && rn >= 0 && rn < R) {
       // row n: (n, 0) with H = 0 first, then its running maximum over j in column order
       const int rowv = (browj > 0) ? brow + n * ge : 0;
-      if (better(rowv, n, browj, bs, bi, bjj)) {
+      const int ci = flip ? browj : n, cj = flip ? n : browj;
+      if (better(rowv, ci, cj, bs, bi, bjj)) {
         bs = rowv;
-        bi = n;
-        bjj = browj;
+        bi = ci;
+        bjj = cj;
       }
     }
     for (int o = 32; o >= 1; o >>= 1) {
@@ -384,7 +426,7 @@ __global__ __launch_bounds__(256) void wf_finish_kernel(const KParams P, WfWs W,
       }
     }
     if (lane != 0) continue;
-    const int n = pr.n, m = pr.m;
+    const int n = pr.flip ? pr.m : pr.n, m = pr.flip ? pr.n : pr.m;  // the call's query and subject lengths
     aln_result_t r;
     r.q_begin = -1;
     r.s_begin = -1;
@@ -434,7 +476,7 @@ __global__ __launch_bounds__(256) void wf_finish_kernel(const KParams P, WfWs W,
   }
 }
 
-// Clears the progress flags of every item and the ticket before a wavefront launch.
+// Clears the progress counter of every item and the ticket before a wavefront launch.
 __global__ void wf_reset_kernel(WfWs W) {
   const int64_t n_items = *W.n_items;
   for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n_items; k += (int64_t)gridDim.x * blockDim.x)
@@ -458,30 +500,40 @@ __global__ void wf_single_pair_kernel(WfWs W, int n, int m, int band_rows) {
     p.row_off = 0;
     p.code_off = 0;
     p.out_idx = 0;
+    p.flip = 0;
+    p.pad_ = 0;
     W.pairs[0] = p;
     *W.n_pairs = 1;
     *W.n_items = p.nb;
   }
 }
 
-template <int MODE, bool AFFINE, bool SMALL, bool TB>
+template <int MODE, bool AFFINE, int PROF, bool TB>
 void launch_wf_t(const KParams& kp, const uint8_t* q, const uint8_t* s, const WfWs& W, int n_waves,
                  hipStream_t stream) {
   const int blocks = (n_waves + kWfWavesPerBlock - 1) / kWfWavesPerBlock;
   ProfScope prof(TB ? "wavefront_i32_traceback" : "wavefront_i32", stream);
-  hipLaunchKernelGGL((wf_i32_kernel<MODE, AFFINE, SMALL, TB, kWfR>), dim3(blocks), dim3(kWfBlock), 0, stream, kp,
+  hipLaunchKernelGGL((wf_i32_kernel<MODE, AFFINE, PROF, TB, kWfR>), dim3(blocks), dim3(kWfBlock), 0, stream, kp,
                      q, s, W);
+}
+
+template <int MODE, bool AFFINE, bool TB>
+void launch_wf_p(const KParams& kp, const uint8_t* q, const uint8_t* s, const WfWs& W, int nw, hipStream_t st) {
+  const bool bytes = kp.sigma_max - kp.ge <= 127 && kp.sigma_min - kp.ge >= -127;
+  if (bytes && kp.alphabet <= 4)
+    launch_wf_t<MODE, AFFINE, kProfReg, TB>(kp, q, s, W, nw, st);
+  else if (bytes)
+    launch_wf_t<MODE, AFFINE, kProfLane, TB>(kp, q, s, W, nw, st);
+  else
+    launch_wf_t<MODE, AFFINE, kProfTable, TB>(kp, q, s, W, nw, st);
 }
 
 template <int MODE, bool TB>
 void launch_wf_m(const KParams& kp, const uint8_t* q, const uint8_t* s, const WfWs& W, int nw, hipStream_t st) {
-  const bool affine = kp.go != 0;
-  // the per-row profile holds sigma - ge in a signed byte
-  const bool small = kp.alphabet <= 4 && kp.sigma_max - kp.ge <= 127 && kp.sigma_min - kp.ge >= -127;
-  if (affine && small) launch_wf_t<MODE, true, true, TB>(kp, q, s, W, nw, st);
-  if (affine && !small) launch_wf_t<MODE, true, false, TB>(kp, q, s, W, nw, st);
-  if (!affine && small) launch_wf_t<MODE, false, true, TB>(kp, q, s, W, nw, st);
-  if (!affine && !small) launch_wf_t<MODE, false, false, TB>(kp, q, s, W, nw, st);
+  if (kp.go != 0)
+    launch_wf_p<MODE, true, TB>(kp, q, s, W, nw, st);
+  else
+    launch_wf_p<MODE, false, TB>(kp, q, s, W, nw, st);
 }
 
 template <int MODE>
@@ -500,9 +552,10 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 }  // namespace
 
-int wf_waves() {
+int wf_waves(int per_cu) {
   const int cus = device_cu_count();
-  return cus > 0 ? cus * kWfWavesPerCU : -1;
+  if (per_cu < 1 || per_cu > kWfWavesPerCUMax) return -1;
+  return cus > 0 ? cus * per_cu : -1;
 }
 
 size_t wf_layout(int64_t max_pairs, int64_t max_items, int64_t row_words, int64_t code_words, WfOffsets* o) {
@@ -561,7 +614,7 @@ aln_status_t launch_wf_i32(const KParams& kp, const WfWs& W, const uint8_t* q, c
 aln_status_t plan_long(int64_t n, int64_t m, bool tb, LongPlan* pl) {
   pl->nb = (n + kWfBand - 1) / kWfBand;
   pl->tb = tb;
-  const int nw = wf_waves();
+  const int nw = wf_waves(kWfWavesPerCUDefault);
   if (nw <= 0) return ALN_E_DEVICE;
   int64_t waves = nw;
   const int64_t want = (pl->nb + kWfWavesPerBlock - 1) / kWfWavesPerBlock * kWfWavesPerBlock;

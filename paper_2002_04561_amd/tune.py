@@ -1,0 +1,109 @@
+"""Autotuner for aln_align_batch_ex: picks the execution choices of a batch by timing them on the device.
+
+The choices (aln_batch_config_t) decide how a batch is laid out on the GPU, never what it computes:
+  wf_min_cells     which pairs run on the band wavefront (one band of 256 rows per wave, many waves per
+                   pair) instead of one pair per lane -- the tile shape / pairs-per-wavefront trade-off;
+  wf_waves_per_cu  how many persistent waves the wavefront engine keeps per compute unit;
+  wf_orient        whether a wavefront pair runs with its longer sequence along the band rows;
+  small_bits       packed 16-bit lanes (two pairs per lane, with the exact overflow check and 32-bit
+                   redo) or 32-bit lanes for the one-pair-per-lane kernels.
+Every candidate gives bit-identical results (the parity tests run the same pairs under several configs),
+so the tuner compares time only.  It searches one coordinate at a time from the library's defaults,
+timing the caller's own batch on the caller's stream with HIP events, and caches the winner under a
+signature of the workload (scoring model, traceback, pair count and the log2 histogram of n*m), so a
+serving loop or a benchmark pays for the search once per kind of batch.
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+from dataclasses import asdict
+from typing import Dict, List, Optional, Tuple
+
+import numpy as np
+
+from . import AlnError, BatchConfig
+
+SEARCH = (
+    ("wf_min_cells", (1 << 20, 1 << 18, 1 << 16, 1 << 14, 1 << 12, 1, -1)),
+    ("wf_waves_per_cu", (8, 4, 12, 16)),
+    ("wf_orient", (1, -1)),
+    ("small_bits", (16, 32)),
+)
+
+_CACHE: Dict[str, dict] = {}
+
+
+def signature(scoring, flags: int, n: np.ndarray, m: np.ndarray) -> str:
+    """Workload key: the scoring model (mode, gap model, alphabet), traceback, pair count (log2) and the
+    log2 histogram of the pairs' cell counts."""
+    cells = n.astype(np.int64) * m.astype(np.int64)
+    hist = np.bincount(np.log2(np.maximum(cells, 1)).astype(int), minlength=40)[:40]
+    hist = np.round(hist / max(len(cells), 1), 2)
+    key = {"mode": scoring.mode, "affine": scoring.gap_open != 0, "alphabet": scoring.alphabet_size,
+           "flags": int(flags), "pairs_log2": int(math.log2(max(len(cells), 1))), "cells_log2_hist": hist.tolist()}
+    return json.dumps(key, sort_keys=True)
+
+
+def _time(ba, cfg: BatchConfig, stream, repeats: int) -> float:
+    import torch
+    ba.config = cfg
+    ba.run(stream)  # warm-up (and validates the config)
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    best = float("inf")
+    for _ in range(repeats):
+        t0.record(stream)
+        ba.run(stream)
+        t1.record(stream)
+        t1.synchronize()
+        best = min(best, t0.elapsed_time(t1))
+    return best
+
+
+def tune(ba, stream=None, repeats: int = 1, log=None, cache_file: Optional[str] = None) -> Tuple[BatchConfig, List]:
+    """Tunes the execution config of a BatchAligner in place (sets ba.config) and returns (config, table).
+
+    `table` lists every candidate timed as (config dict, milliseconds).  The batch is run several times; its
+    output buffers hold the last run's (identical) results afterwards."""
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    qo = ba.q_off.to("cpu").numpy()
+    so = ba.s_off.to("cpu").numpy()
+    sig = signature(ba.scoring, ba.flags, qo[1:] - qo[:-1], so[1:] - so[:-1])
+    if cache_file and os.path.exists(cache_file):
+        with open(cache_file) as fh:
+            _CACHE.update(json.load(fh))
+    if sig in _CACHE:
+        cfg = BatchConfig(**_CACHE[sig]["config"])
+        ba.config = cfg
+        return cfg, _CACHE[sig]["table"]
+    cur = BatchConfig(wf_min_cells=1 << 20, wf_waves_per_cu=8, wf_orient=1, small_bits=16)
+    seen: Dict[BatchConfig, float] = {}
+
+    def measure(cfg):
+        if cfg not in seen:
+            try:
+                seen[cfg] = _time(ba, cfg, stream, repeats)
+            except AlnError:
+                seen[cfg] = float("inf")
+            if log:
+                log("tune %s: %.3f ms" % (asdict(cfg), seen[cfg]))
+        return seen[cfg]
+
+    best_ms = measure(cur)
+    for field, values in SEARCH:
+        for v in values:
+            cand = BatchConfig(**{**asdict(cur), field: v})
+            ms = measure(cand)
+            if ms < best_ms:
+                cur, best_ms = cand, ms
+    ba.config = cur
+    table = [(asdict(c), ms) for c, ms in seen.items()]
+    _CACHE[sig] = {"config": asdict(cur), "table": table}
+    if cache_file:
+        with open(cache_file, "w") as fh:
+            json.dump(_CACHE, fh)
+    return cur, table

@@ -24,7 +24,7 @@ def run_oracle(w: synth.Workload, traceback: bool, threads=None):
     return res, cigars
 
 
-def run_gpu(w: synth.Workload, flags: int, max_n=None, max_m=None, stream=None):
+def run_gpu(w: synth.Workload, flags: int, max_n=None, max_m=None, stream=None, config=None):
     import torch
 
     import paper_2002_04561_amd as aln
@@ -32,7 +32,7 @@ def run_gpu(w: synth.Workload, flags: int, max_n=None, max_m=None, stream=None):
     max_n = int(n.max()) if max_n is None and len(n) else (max_n or 0)
     max_m = int(m.max()) if max_m is None and len(m) else (max_m or 0)
     q, qo, s, so = aln.to_device(w)
-    ba = aln.BatchAligner(aln.scoring_of(w), q, qo, s, so, max_n, max_m, flags)
+    ba = aln.BatchAligner(aln.scoring_of(w), q, qo, s, so, max_n, max_m, flags, config=config)
     ba.run(stream)
     torch.cuda.synchronize()
     res = ba.results()

@@ -156,3 +156,52 @@ def test_int16_equals_int32(gpu, mode, scheme):
     for k in range(w.n_pairs):
         assert tuple(a[k])[:6] == tuple(b[k])[:6] and ac[k] == bc[k], k
     assert not np.any(a["flags"] & aln.RES_INT32_REDO)
+
+
+ASYM3 = np.array([[2, -1, -3], [0, 1, -2], [-2, 3, 1]], dtype=np.int8)  # sigma(q, s) != sigma(s, q)
+WF_SCHEMES = {
+    # register profile (alphabet <= 4), asymmetric table, ties likely
+    "asym3_affine": (3, None, None, ASYM3, -2, -1),
+    # per-lane LDS profile (alphabet 20)
+    "prot_affine": SCHEMES["prot_affine"],
+    "prot_linear": SCHEMES["prot_linear"],
+    # sigma - ge beyond a signed byte: the 32-bit LDS table
+    "dna_bigscore": (4, 100, -60, None, -50, -30),
+}
+
+
+@pytest.mark.parametrize("mode", [0, 1, 2], ids=["global", "local", "semi"])
+@pytest.mark.parametrize("scheme", list(WF_SCHEMES))
+@pytest.mark.parametrize("orient", [1, -1], ids=["oriented", "as_given"])
+def test_wavefront_every_pair(gpu, mode, scheme, orient):
+    """Every non-empty pair on the band wavefront (wf_min_cells = 1), lengths log-uniform 1..1500 in both
+    directions, so that pairs run transposed (orient = 1, the longer sequence along the rows) or as given;
+    results must not depend on it, ties included."""
+    import paper_2002_04561_amd as aln
+    A, ma, mi, sub, go, ge = WF_SCHEMES[scheme]
+    rng = np.random.default_rng(700 + 10 * mode + len(scheme) + (orient > 0))
+    lens = np.rint(np.exp(rng.uniform(0, np.log(1500), (90, 2)))).astype(int)
+    lens[:6] = [(1, 1), (1, 700), (700, 1), (0, 40), (40, 0), (257, 1300)]
+    qs = [rng.integers(0, A, a, dtype=np.uint8) for a, _ in lens]
+    ss = [synth.mutate_geometric(rng, qs[k], 0.1, 0.02, 2.0, A)[:b] if k % 2 == 0 and b <= len(qs[k]) else
+          rng.integers(0, A, b, dtype=np.uint8) for k, (_, b) in enumerate(lens)]
+    q, qo = synth.pack(qs)
+    s, so = synth.pack(ss)
+    w = synth.Workload("wf_" + scheme, mode, A, go, ge, q, qo, s, so, match=ma, mismatch=mi, subst=sub)
+    cfg = aln.BatchConfig(wf_min_cells=1, wf_orient=orient)
+    gres, _ = run_gpu(w, aln.SCORE_ONLY, config=cfg)
+    ores, _ = run_oracle(w, False)
+    bad = compare(w, gres, None, ores, None, "wf/%s/%d" % (scheme, orient))
+    assert not bad, "\n".join(bad[:10])
+
+
+@pytest.mark.parametrize("waves", [1, 4, 16])
+def test_wavefront_waves_per_cu(gpu, waves):
+    """The persistent grid size changes nothing: few waves per CU (long queues) and many."""
+    import paper_2002_04561_amd as aln
+    w = _workload(880 + waves, 120, 100, 2500, 1, "prot_affine")
+    cfg = aln.BatchConfig(wf_min_cells=1 << 14, wf_waves_per_cu=waves)
+    gres, _ = run_gpu(w, aln.SCORE_ONLY, config=cfg)
+    ores, _ = run_oracle(w, False)
+    bad = compare(w, gres, None, ores, None, "waves %d" % waves)
+    assert not bad, "\n".join(bad[:10])
