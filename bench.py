@@ -196,13 +196,21 @@ def time_per_bin(w, flags, stream, steps, config=None):
 
 
 def time_plain(w, flags, stream, count, seed=1):
-    """One pair per call: a random sample of pairs, each aligned by its own aln_align_batch call (each call
-    waits for the previous); GCUPS = sample cells / summed time."""
+    """One pair per call: a random sample of pairs, each aligned by its own aln_align_long call (the
+    single-pair entry point: the pair's rows in bands across the device), each call waiting for the
+    previous; GCUPS = sample cells / summed time."""
     import torch
+
+    import paper_2002_04561_amd as aln
     rng = np.random.default_rng(seed)
     idx = np.sort(rng.choice(w.n_pairs, size=min(count, w.n_pairs), replace=False))
     n, m = w.lengths()
-    calls = [_sub_aligner(w, [k], flags)[0] for k in idx]
+    sc = aln.scoring_of(w)
+    calls = []
+    for k in idx:
+        a, b = w.pair(int(k))
+        calls.append(aln.LongAligner(sc, torch.from_numpy(a.copy()).cuda(), torch.from_numpy(b.copy()).cuda(),
+                                     flags))
     for ba in calls[:4]:
         ba.run(stream)
     torch.cuda.synchronize()
@@ -213,7 +221,7 @@ def time_plain(w, flags, stream, count, seed=1):
     dt = time.perf_counter() - t0
     cells = float(np.sum(n[idx].astype(np.int64) * m[idx]))
     return {"gcups": round(cells / dt / 1e9, 2), "pairs": len(idx), "cells": cells, "seconds": round(dt, 4),
-            "sample": "%d random pairs, one aln_align_batch call per pair, synchronised" % len(idx)}
+            "sample": "%d random pairs, one aln_align_long call per pair, synchronised" % len(idx)}
 
 
 def serve_stream(n_req, rate_hz, seed=5, long_len=65536):

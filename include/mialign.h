@@ -137,10 +137,13 @@ aln_status_t aln_align_batch(const aln_scoring_t* scoring, int64_t n_pairs, cons
  * zero field selects the default.
  *   wf_min_cells     score-only calls: pairs with n*m >= wf_min_cells run on the band wavefront
  *                    engine, the others one pair per lane.  0 => 2^20; negative => no pair.
- *   wf_waves_per_cu  persistent waves per compute unit of the wavefront engine, 1..16; 0 => 8.
- *   wf_orient        score-only calls: 1 => a wavefront pair runs with its longer sequence along
- *                    the band rows (the transposed problem has the same optimum; ties are still
- *                    resolved in the (i, j) order of the call); -1 => as given.  0 => 1.
+ *   wf_waves_per_cu  persistent waves per compute unit of the wavefront engine, 1..32; 0 => 8
+ *                    (waves beyond what a compute unit holds start as others finish).
+ *   wf_orient        score-only calls: how a wavefront pair is laid out.  The transposed problem
+ *                    has the same optimum, and ties are still resolved in the (i, j) order of the
+ *                    call.  1 => longer sequence along the band rows; -1 => as given; 2 => whichever
+ *                    takes fewer band steps, ceil(rows / 256) * (columns + 127), except that a pair
+ *                    of several bands is never laid out with the longer sequence as columns.  0 => 2.
  *   small_bits       one-pair-per-lane kernels: 16 => packed 16-bit lanes where provably exact,
  *                    with the 32-bit redo; 32 => 32-bit lanes only.  0 => 16. */
 typedef struct {

@@ -39,6 +39,12 @@ __device__ __forceinline__ int log_bin(int64_t x) {
   return b < kShapeBins ? b : kShapeBins - 1;
 }
 
+// Wave-steps the band wavefront spends on a rows x cols problem: one band per 256 rows, each
+// sweeping cols + 63 steps plus a start-up of about 64 steps (ticket, pair lookup, profile).
+__device__ __forceinline__ int64_t band_steps(int64_t rows, int64_t cols) {
+  return (rows + kWfBand - 1) / kWfBand * (cols + 63 + 64);
+}
+
 __global__ void split_reset_kernel(SplitView V) {
   for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < kKeys; k += gridDim.x * blockDim.x) V.hist[k] = 0;
   if (blockIdx.x == 0 && threadIdx.x < 2) V.counters[threadIdx.x] = 0;
@@ -106,7 +112,11 @@ __global__ void sort_scatter_kernel(int64_t n_pairs, const int64_t* __restrict__
     }
     const int64_t qb = q_off[p], sb = s_off[p];
     const int32_t n = (int32_t)(q_off[p + 1] - qb), m = (int32_t)(s_off[p + 1] - sb);
-    const bool flip = orient && m > n;
+    // Row slots (2 (columns + 1) entries) are reserved from the subject total, so a pair of two or
+    // more bands may only be flipped to shorter columns; a one-band pair needs no slots.
+    bool flip = false;
+    if (orient == 1) flip = m > n;
+    if (orient == 2) flip = band_steps(m, n) < band_steps(n, m) && (n <= m || m <= kWfBand);
     WfPair pr;
     pr.q_off = flip ? sb : qb;
     pr.s_off = flip ? qb : sb;
@@ -124,7 +134,10 @@ __global__ void sort_scatter_kernel(int64_t n_pairs, const int64_t* __restrict__
 }
 
 // One block: exclusive prefix sums of the bands (item0) and row slots (row_off) of the big pairs.
-__global__ __launch_bounds__(1024) void split_scan_kernel(SplitView V, WfWs W) {
+// Should the totals exceed what the workspace was sized for (the caller understated total_q or
+// total_s), the wavefront pairs are dropped and their results flagged instead.
+__global__ __launch_bounds__(1024) void split_scan_kernel(SplitView V, WfWs W, int64_t item_cap, int64_t row_cap,
+                                                          aln_result_t* __restrict__ out) {
   __shared__ int64_t s_items[1024], s_rows[1024];
   const int np = V.counters[1];
   int64_t base_items = 0, base_rows = 0;
@@ -133,7 +146,7 @@ __global__ __launch_bounds__(1024) void split_scan_kernel(SplitView V, WfWs W) {
     int64_t it = 0, rw = 0;
     if (k < np) {
       it = W.pairs[k].nb;
-      rw = 2 * ((int64_t)W.pairs[k].m + 1);
+      rw = it >= 2 ? 2 * ((int64_t)W.pairs[k].m + 1) : 0;  // one band: no hand-off
     }
     s_items[threadIdx.x] = it;
     s_rows[threadIdx.x] = rw;
@@ -154,9 +167,22 @@ __global__ __launch_bounds__(1024) void split_scan_kernel(SplitView V, WfWs W) {
     base_rows += s_rows[1023];
     __syncthreads();
   }
+  const bool fits = base_items <= item_cap && base_rows <= row_cap;
+  if (!fits) {
+    for (int k = threadIdx.x; k < np; k += blockDim.x) {
+      aln_result_t r;
+      r.score = 0;
+      r.q_begin = r.s_begin = -1;
+      r.q_end = r.s_end = 0;
+      r.cigar_len = 0;
+      r.flags = ALN_RES_DEVICE_ERROR;
+      r.reserved = 0;
+      out[W.pairs[k].out_idx] = r;
+    }
+  }
   if (threadIdx.x == 0) {
-    *W.n_items = base_items;
-    *W.n_pairs = np;
+    *W.n_items = fits ? base_items : 0;
+    *W.n_pairs = fits ? np : 0;
   }
 }
 
@@ -168,13 +194,14 @@ BatchCfg resolve_cfg(const aln_batch_config_t* c) {
   BatchCfg r;
   r.wf_min_cells = (int64_t)1 << 20;
   r.wf_waves_per_cu = kWfWavesPerCUDefault;
-  r.orient = true;
+  r.orient = 2;
   r.small16 = true;
   if (!c) return r;
   if (c->wf_min_cells < 0) r.wf_min_cells = INT64_MAX;
   if (c->wf_min_cells > 0) r.wf_min_cells = c->wf_min_cells;
   if (c->wf_waves_per_cu > 0) r.wf_waves_per_cu = c->wf_waves_per_cu;
-  if (c->wf_orient < 0) r.orient = false;
+  if (c->wf_orient < 0) r.orient = 0;
+  if (c->wf_orient == 1) r.orient = 1;
   if (c->small_bits == 32) r.small16 = false;
   return r;
 }
@@ -182,7 +209,7 @@ BatchCfg resolve_cfg(const aln_batch_config_t* c) {
 aln_status_t plan_split(int64_t n_pairs, int64_t total_q, int64_t total_s, bool route_big, const BatchCfg& cfg,
                         SplitPlan* sp) {
   sp->big_cells = route_big ? cfg.wf_min_cells : INT64_MAX;
-  sp->orient = cfg.orient ? 1 : 0;
+  sp->orient = cfg.orient;
   size_t off = 0;
   sp->off_small_idx = off;
   off += align256((size_t)(n_pairs + 1) * sizeof(int));
@@ -195,15 +222,17 @@ aln_status_t plan_split(int64_t n_pairs, int64_t total_q, int64_t total_s, bool 
   sp->wf_base = off;
   // bands run along the longer side when oriented: at most (n + m) / band + 1 per pair
   const int64_t max_items = (total_q + total_s) / kWfBand + n_pairs + 1;
-  // a pair's row slots span its columns, min(n, m) + 1 when oriented: at most m + 1 either way
-  off += wf_layout(n_pairs + 1, max_items, 2 * (total_s + n_pairs), 0, &sp->wf);
+  // a pair of two or more bands has row slots over its columns, never more than m + 1 of them
+  sp->item_cap = max_items;
+  sp->row_cap = 2 * (total_s + n_pairs);
+  off += wf_layout(n_pairs + 1, max_items, sp->row_cap, 0, &sp->wf);
   sp->total_bytes = off;
   sp->wf_waves = wf_waves(cfg.wf_waves_per_cu);
   return sp->wf_waves > 0 ? ALN_OK : ALN_E_DEVICE;
 }
 
 void launch_split(const SplitPlan& sp, int64_t n_pairs, const int64_t* q_off, const int64_t* s_off, int64_t max_n,
-                  int64_t max_m, void* ws, hipStream_t stream) {
+                  int64_t max_m, aln_result_t* out, void* ws, hipStream_t stream) {
   char* base = static_cast<char*>(ws);
   SplitView V;
   V.small_idx = reinterpret_cast<int*>(base + sp.off_small_idx);
@@ -219,7 +248,7 @@ void launch_split(const SplitPlan& sp, int64_t n_pairs, const int64_t* q_off, co
                      sp.big_cells, V);
   hipLaunchKernelGGL(sort_scan_kernel, dim3(1), dim3(kScanThreads), 0, stream, V);
   hipLaunchKernelGGL(sort_scatter_kernel, grid, dim3(256), 0, stream, n_pairs, q_off, s_off, sp.orient, V, W);
-  hipLaunchKernelGGL(split_scan_kernel, dim3(1), dim3(1024), 0, stream, V, W);
+  hipLaunchKernelGGL(split_scan_kernel, dim3(1), dim3(1024), 0, stream, V, W, sp.item_cap, sp.row_cap, out);
 }
 
 }  // namespace mialign

@@ -75,6 +75,7 @@ struct WfWs {
   WfPair* pairs;     // [n_pairs], item0 ascending
   int2* rows;        // row slots of all pairs
   int* flags;        // [n_items] columns of each band's bottom row published so far
+  int* item_pair;    // [n_items] index in `pairs` of each band's pair
   int4* band_res;    // [n_items] (score, i, j, flags) optimum of each band
   int64_t* ticket;   // item dispenser
   int64_t* n_items;  // total bands (device value, written by the planner)
@@ -84,7 +85,7 @@ struct WfWs {
 };
 
 struct WfOffsets {
-  size_t pairs, rows, flags, res, misc, codes;
+  size_t pairs, rows, flags, item_pair, res, misc, codes;
 };
 
 struct LongPlan {
@@ -138,7 +139,7 @@ aln_status_t launch_batch_i16(const KParams& kp, const BatchPlan16& plan, const 
 
 // wf_i32.hip
 constexpr int kWfWavesPerCUDefault = 8;
-constexpr int kWfWavesPerCUMax = 16;
+constexpr int kWfWavesPerCUMax = 32;
 int wf_waves(int per_cu);
 size_t wf_layout(int64_t max_pairs, int64_t max_items, int64_t row_words, int64_t code_words, WfOffsets* o);
 WfWs wf_view(void* base, const WfOffsets& o);
@@ -152,7 +153,8 @@ aln_status_t launch_long(const KParams& kp, const LongPlan& plan, const uint8_t*
 // batch_plan.hip
 struct SplitPlan {
   int64_t big_cells;  // pairs with n*m >= big_cells go to the wavefront engine
-  int orient;         // wavefront pairs run with the longer sequence along the rows
+  int orient;         // wavefront pair orientation: 1 longer sequence along the rows, 0 as given, 2 cheaper
+  int64_t item_cap, row_cap;  // bands and row-slot entries the workspace holds
   WfOffsets wf;
   size_t off_small_idx, off_small_cnt, off_keys, off_hist, wf_base, total_bytes;
   int wf_waves;
@@ -161,13 +163,13 @@ struct SplitPlan {
 struct BatchCfg {
   int64_t wf_min_cells;
   int wf_waves_per_cu;
-  bool orient;
+  int orient;  // 1 longer along the rows, 0 as given, 2 the cheaper of the two
   bool small16;
 };
 BatchCfg resolve_cfg(const aln_batch_config_t* c);
 aln_status_t plan_split(int64_t n_pairs, int64_t total_q, int64_t total_s, bool route_big, const BatchCfg& cfg,
                         SplitPlan* sp);
 void launch_split(const SplitPlan& sp, int64_t n_pairs, const int64_t* q_off, const int64_t* s_off, int64_t max_n,
-                  int64_t max_m, void* ws, hipStream_t stream);
+                  int64_t max_m, aln_result_t* out, void* ws, hipStream_t stream);
 
 }  // namespace mialign

@@ -63,16 +63,15 @@ template <int MODE, bool AFFINE, int PROF, bool TB, int R>
 __global__ __launch_bounds__(kWfBlock) void wf_i32_kernel(const KParams P, const uint8_t* __restrict__ Q,
                                                           const uint8_t* __restrict__ S, WfWs W) {
   static_assert(PROF != kProfLane || R == 4, "a lane profile word holds 4 rows");
-  __shared__ int32_t tab[PROF == kProfTable ? kTab * kTab : 1];
-  __shared__ uint32_t lprof[PROF == kProfLane ? kWfWavesPerBlock * kMaxAlphabet * 64 : 1];
+  // sigma - ge by (query letter, subject letter); also the source of the byte profiles
+  __shared__ int32_t tab[kTab * kTab];
   __shared__ int4 stage[kWfWavesPerBlock][3][16];  // lane-0 inputs of 64 steps: H, E, letter
-  if (PROF == kProfTable) {
-    for (int k = threadIdx.x; k < kTab * kTab; k += blockDim.x) {
-      const int a = k / kTab, b = k % kTab;
-      tab[k] = (a >= P.alphabet || b >= P.alphabet) ? -kBig32 : (int32_t)P.sig[a * kMaxAlphabet + b] - P.ge;
-    }
-    __syncthreads();
+  extern __shared__ uint32_t lprof[];               // kProfLane: [wave][letter][lane], alphabet letters
+  for (int k = threadIdx.x; k < kTab * kTab; k += blockDim.x) {
+    const int a = k / kTab, b = k % kTab;
+    tab[k] = (a >= P.alphabet || b >= P.alphabet) ? -kBig32 : (int32_t)P.sig[a * kMaxAlphabet + b] - P.ge;
   }
+  __syncthreads();
   constexpr int BH = 64 * R;
   const int lane = threadIdx.x & 63;
   const int wib = threadIdx.x >> 6;
@@ -89,16 +88,7 @@ __global__ __launch_bounds__(kWfBlock) void wf_i32_kernel(const KParams P, const
     t = __shfl(t, 0, 64);
     if (t >= n_items) break;
     if (__hip_atomic_load(W.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
-    // the pair owning item t: last k with pairs[k].item0 <= t
-    int lo = 0, hi = np - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (W.pairs[mid].item0 <= t)
-        lo = mid;
-      else
-        hi = mid - 1;
-    }
-    const WfPair pr = W.pairs[lo];
+    const WfPair pr = W.pairs[np == 1 ? 0 : W.item_pair[t]];
     const int b = (int)(t - pr.item0);
     const int n = pr.n, m = pr.m, nb = pr.nb;
     // rows come from the query array, columns from the subject array, or the reverse when flipped
@@ -106,10 +96,8 @@ __global__ __launch_bounds__(kWfBlock) void wf_i32_kernel(const KParams P, const
     const uint8_t* __restrict__ q = (flip ? S : Q) + pr.q_off;
     const uint8_t* __restrict__ s = (flip ? Q : S) + pr.s_off;
     const int64_t ld = (int64_t)m + 1;
-    // sigma of a (row letter, column letter) pair, in the call's (query, subject) order
-    auto sig_rc = [&](int cr, int cc) -> int {
-      return flip ? (int)P.sig[cc * kMaxAlphabet + cr] : (int)P.sig[cr * kMaxAlphabet + cc];
-    };
+    // sigma - ge of a (row letter, column letter) pair, taken in the call's (query, subject) order
+    auto sig_rc = [&](int cr, int cc) -> int { return flip ? tab[cc * kTab + cr] : tab[cr * kTab + cc]; };
 
     const int i0 = b * BH;
     int prof[R];  // kProfReg: 4 bytes sigma - ge against letters 0..3; kProfTable: table offset of the letter
@@ -132,7 +120,7 @@ __global__ __launch_bounds__(kWfBlock) void wf_i32_kernel(const KParams P, const
       if (PROF == kProfReg) {
         uint32_t w = 0;
         for (int a = 0; a < 4; ++a) {
-          const int v = (c < P.alphabet && a < P.alphabet) ? sig_rc(c, a) - ge : -128;
+          const int v = (c < P.alphabet && a < P.alphabet) ? sig_rc(c, a) : -128;
           w |= ((uint32_t)(v & 0xff)) << (8 * a);
         }
         prof[r] = (int)w;
@@ -147,14 +135,14 @@ __global__ __launch_bounds__(kWfBlock) void wf_i32_kernel(const KParams P, const
       bv[r] = kNeg32;
       bj[r] = 0;
     }
-    uint32_t* __restrict__ lp = lprof + (PROF == kProfLane ? wib * kMaxAlphabet * 64 + lane : 0);
+    uint32_t* __restrict__ lp = lprof + (PROF == kProfLane ? wib * P.alphabet * 64 + lane : 0);
     if (PROF == kProfLane) {
       // this lane's word per column letter; each lane reads only its own words, so no barrier
       for (int a = 0; a < P.alphabet; ++a) {
         uint32_t w = 0;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-          const int v = rowc[r] < P.alphabet ? sig_rc(rowc[r], a) - ge : -128;
+          const int v = rowc[r] < P.alphabet ? sig_rc(rowc[r], a) : -128;
           w |= ((uint32_t)(v & 0xff)) << (8 * r);
         }
         lp[a * 64] = w;
@@ -476,11 +464,17 @@ __global__ __launch_bounds__(256) void wf_finish_kernel(const KParams P, WfWs W,
   }
 }
 
-// Clears the progress counter of every item and the ticket before a wavefront launch.
+// Before a wavefront launch: clears the progress counter of every item and the ticket, and maps
+// every item to its pair.
 __global__ void wf_reset_kernel(WfWs W) {
   const int64_t n_items = *W.n_items;
-  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n_items; k += (int64_t)gridDim.x * blockDim.x)
-    W.flags[k] = 0;
+  const int np = *W.n_pairs;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n_items; k += stride) W.flags[k] = 0;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < np; k += stride) {
+    const WfPair pr = W.pairs[k];
+    for (int b = 0; b < pr.nb; ++b) W.item_pair[pr.item0 + b] = (int)k;
+  }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     *W.ticket = 0;
     *W.error = 0;
@@ -512,8 +506,9 @@ template <int MODE, bool AFFINE, int PROF, bool TB>
 void launch_wf_t(const KParams& kp, const uint8_t* q, const uint8_t* s, const WfWs& W, int n_waves,
                  hipStream_t stream) {
   const int blocks = (n_waves + kWfWavesPerBlock - 1) / kWfWavesPerBlock;
+  const size_t lds = PROF == kProfLane ? (size_t)kWfWavesPerBlock * kp.alphabet * 64 * sizeof(uint32_t) : 0;
   ProfScope prof(TB ? "wavefront_i32_traceback" : "wavefront_i32", stream);
-  hipLaunchKernelGGL((wf_i32_kernel<MODE, AFFINE, PROF, TB, kWfR>), dim3(blocks), dim3(kWfBlock), 0, stream, kp,
+  hipLaunchKernelGGL((wf_i32_kernel<MODE, AFFINE, PROF, TB, kWfR>), dim3(blocks), dim3(kWfBlock), lds, stream, kp,
                      q, s, W);
 }
 
@@ -566,6 +561,8 @@ size_t wf_layout(int64_t max_pairs, int64_t max_items, int64_t row_words, int64_
   off += align256((size_t)row_words * sizeof(int2));
   o->flags = off;
   off += align256((size_t)(max_items + 1) * sizeof(int));
+  o->item_pair = off;
+  off += align256((size_t)(max_items + 1) * sizeof(int));
   o->res = off;
   off += align256((size_t)(max_items + 1) * sizeof(int4));
   o->misc = off;
@@ -581,6 +578,7 @@ WfWs wf_view(void* base_, const WfOffsets& o) {
   W.pairs = reinterpret_cast<WfPair*>(base + o.pairs);
   W.rows = reinterpret_cast<int2*>(base + o.rows);
   W.flags = reinterpret_cast<int*>(base + o.flags);
+  W.item_pair = reinterpret_cast<int*>(base + o.item_pair);
   W.band_res = reinterpret_cast<int4*>(base + o.res);
   W.ticket = reinterpret_cast<int64_t*>(base + o.misc);
   W.n_items = reinterpret_cast<int64_t*>(base + o.misc + 8);

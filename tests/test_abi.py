@@ -54,10 +54,11 @@ def test_scoring_validation_on_host():
 def test_batch_config_validation_on_host():
     """aln_align_batch_ex rejects out-of-range execution choices before any device work."""
     sc = aln.Scoring(0, 4, 0, -1, 1, -1).c()
-    cases = [(aln.BatchConfig(wf_waves_per_cu=17), -1), (aln.BatchConfig(wf_waves_per_cu=-1), -1),
-             (aln.BatchConfig(wf_orient=2), -1), (aln.BatchConfig(small_bits=8), -1),
-             (aln.BatchConfig(), 0), (aln.BatchConfig(wf_min_cells=-1, wf_waves_per_cu=16, wf_orient=-1,
-                                                      small_bits=32), 0)]
+    cases = [(aln.BatchConfig(wf_waves_per_cu=33), -1), (aln.BatchConfig(wf_waves_per_cu=-1), -1),
+             (aln.BatchConfig(wf_orient=3), -1), (aln.BatchConfig(wf_orient=-2), -1),
+             (aln.BatchConfig(small_bits=8), -1), (aln.BatchConfig(), 0),
+             (aln.BatchConfig(wf_min_cells=-1, wf_waves_per_cu=32, wf_orient=-1, small_bits=32), 0),
+             (aln.BatchConfig(wf_orient=2), 0)]
     for cfg, e in cases:
         c = cfg.c()
         st = aln.lib().aln_align_batch_ex(ctypes.byref(sc), 0, None, None, None, None, 0, 0, 0, 0, 0, ctypes.byref(c),

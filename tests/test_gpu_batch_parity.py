@@ -172,7 +172,7 @@ WF_SCHEMES = {
 
 @pytest.mark.parametrize("mode", [0, 1, 2], ids=["global", "local", "semi"])
 @pytest.mark.parametrize("scheme", list(WF_SCHEMES))
-@pytest.mark.parametrize("orient", [1, -1], ids=["oriented", "as_given"])
+@pytest.mark.parametrize("orient", [1, -1, 2], ids=["oriented", "as_given", "cheaper"])
 def test_wavefront_every_pair(gpu, mode, scheme, orient):
     """Every non-empty pair on the band wavefront (wf_min_cells = 1), lengths log-uniform 1..1500 in both
     directions, so that pairs run transposed (orient = 1, the longer sequence along the rows) or as given;
@@ -195,7 +195,7 @@ def test_wavefront_every_pair(gpu, mode, scheme, orient):
     assert not bad, "\n".join(bad[:10])
 
 
-@pytest.mark.parametrize("waves", [1, 4, 16])
+@pytest.mark.parametrize("waves", [1, 4, 16, 32])
 def test_wavefront_waves_per_cu(gpu, waves):
     """The persistent grid size changes nothing: few waves per CU (long queues) and many."""
     import paper_2002_04561_amd as aln
@@ -205,3 +205,30 @@ def test_wavefront_waves_per_cu(gpu, waves):
     ores, _ = run_oracle(w, False)
     bad = compare(w, gres, None, ores, None, "waves %d" % waves)
     assert not bad, "\n".join(bad[:10])
+
+
+def test_understated_totals_flag_wavefront_pairs(gpu):
+    """total_q / total_s below the real sums leave the workspace too small for the wavefront pairs' bands
+    and row slots; the planner's capacity check drops those pairs with ALN_RES_DEVICE_ERROR instead of
+    overrunning the workspace, and the one-pair-per-lane pairs still come back exact."""
+    import torch
+
+    import paper_2002_04561_amd as aln
+    rng = np.random.default_rng(41)
+    qs = [rng.integers(0, 4, 1500 if k % 4 == 0 else 60, dtype=np.uint8) for k in range(24)]
+    ss = [rng.integers(0, 4, 1400 if k % 4 == 0 else 70, dtype=np.uint8) for k in range(24)]
+    q, qo = synth.pack(qs)
+    s, so = synth.pack(ss)
+    w = synth.Workload("understated", 1, 4, -3, -1, q, qo, s, so, match=2, mismatch=-3)
+    dq, dqo, ds, dso = aln.to_device(w)
+    ba = aln.BatchAligner(aln.scoring_of(w), dq, dqo, ds, dso, 1500, 1400, aln.SCORE_ONLY, total_q=64, total_s=64)
+    ba.run()
+    torch.cuda.synchronize()
+    res = ba.results()
+    ores, _ = run_oracle(w, False)
+    for k in range(w.n_pairs):
+        if k % 4 == 0:
+            assert res["flags"][k] & aln.RES_DEVICE_ERROR, k
+        else:
+            assert (res["score"][k], res["q_end"][k], res["s_end"][k]) == (ores["score"][k], ores["q_end"][k],
+                                                                          ores["s_end"][k]), k
