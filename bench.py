@@ -247,7 +247,7 @@ def serve_stream(n_req, rate_hz, seed=5, long_len=65536):
             b = synth.mutate_geometric(rng, a, 0.05, 0.01, 3.0)[:long_len]
             if len(b) < long_len:
                 b = np.concatenate([b, rng.integers(0, 4, long_len - len(b), dtype=np.uint8)])
-            reqs.append(Request(k, "long", a, b, t, long=True))
+            reqs.append(Request(k, "long", a, b, t))  # batched: the bands of all its pairs share one queue
     return reqs, sig
 
 
@@ -264,8 +264,11 @@ def run_serve(args):
     torch.cuda.set_device(0)
     warm, _ = serve_stream(64, 1e6, seed=99, long_len=4096)
     AlignServer(sc, budget_bytes=args.budget_gb << 30).run(warm, realtime=False)
-    srv = AlignServer(sc, budget_bytes=args.budget_gb << 30, streams=3, max_pairs=8192)
+    srv = AlignServer(sc, budget_bytes=args.budget_gb << 30, streams=3, max_pairs=8192,
+                      class_max_pairs={"long": 8})
+    t_gen = time.perf_counter()
     st = srv.run(reqs, realtime=True)
+    print("[bench] served %d requests in %.1f s" % (st["requests"], time.perf_counter() - t_gen), file=sys.stderr)
     out = {
         "metric": "GCUPS (batched vs plain, bit-exact) on one MI355X; p50/p99 request latency",
         "value": round(st["gcups"], 2), "unit": "GCUPS", "n_gpus": 1, "steps": 1, "warmup": 1,
@@ -273,7 +276,7 @@ def run_serve(args):
         "vs_baseline": None, "dtype": "int16+int32", "data": "synthetic (seeded generator)",
         "config": {"workload": "serve", "requests": len(reqs), "rate_per_s": args.rate, "cells": st["cells"],
                    "budget_bytes": st["budget_bytes"], "peak_bytes": st["peak_bytes"]},
-        "latency_ms": st["classes"],
+        "latency_ms": st["classes"], "int32_redo_requests": st["int32_redo"],
     }
     print(json.dumps(out), flush=True)
 
@@ -292,6 +295,9 @@ def main():
     ap.add_argument("--pairs", type=int, default=None, help="override the pair count of a batch workload")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="batch workloads: library defaults instead of autotuning")
+    ap.add_argument("--config", default=None,
+                    help="batch workloads: a fixed aln_batch_config_t as JSON (no autotuning), e.g. "
+                         "'{\"wf_min_cells\": 1, \"wf_waves_per_cu\": 32, \"wf_orient\": 2}'")
     ap.add_argument("--no-compare", action="store_true",
                     help="batch workloads: skip the graph / per-length-bin / one-pair-per-call comparisons")
     ap.add_argument("--no-check", action="store_true")
@@ -339,7 +345,10 @@ def main():
     torch.cuda.synchronize()
     log("device buffers ready; workspace %.3g GB" % (ba.ws_bytes / 1e9))
     tuned = None
-    if not long_path and not args.no_tune:
+    if not long_path and args.config:
+        ba.config = aln.BatchConfig(**json.loads(args.config))
+        tuned = {"config": ba.config.__dict__, "seconds": 0.0, "candidates": 0, "fixed": True}
+    elif not long_path and not args.no_tune:
         from paper_2002_04561_amd import tune
         t0 = time.perf_counter()
         cfg, table = tune.tune(ba, stream, log=log)

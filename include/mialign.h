@@ -112,7 +112,7 @@ aln_status_t aln_batch_workspace_size(const aln_scoring_t* scoring, int64_t n_pa
                                       size_t* bytes);
 
 /* Aligns n_pairs independent pairs.  Small pairs run one pair per lane (inter-sequence parallelism,
- * Sec. VI); in score-only calls, pairs with n*m >= 2^20 run on the band wavefront of aln_align_long
+ * Sec. VI); in score-only calls, pairs with n*m >= 2^16 run on the band wavefront of aln_align_long
  * instead, all of them sharing one device-wide work queue (the dynamic wavefront of Sec. IV-A),
  * largest first.  The routing is decided on the device, so the host needs no copy of the lengths;
  * aln_align_batch_ex sets the threshold and the other execution choices.
@@ -136,14 +136,15 @@ aln_status_t aln_align_batch(const aln_scoring_t* scoring, int64_t n_pairs, cons
  * out on the device; an autotuner (paper_2002_04561_amd/tune.py) searches them per workload.  A
  * zero field selects the default.
  *   wf_min_cells     score-only calls: pairs with n*m >= wf_min_cells run on the band wavefront
- *                    engine, the others one pair per lane.  0 => 2^20; negative => no pair.
- *   wf_waves_per_cu  persistent waves per compute unit of the wavefront engine, 1..32; 0 => 8
+ *                    engine, the others one pair per lane.  0 => 2^16; negative => no pair.
+ *   wf_waves_per_cu  persistent waves per compute unit of the wavefront engine, 1..32; 0 => 16
  *                    (waves beyond what a compute unit holds start as others finish).
  *   wf_orient        score-only calls: how a wavefront pair is laid out.  The transposed problem
  *                    has the same optimum, and ties are still resolved in the (i, j) order of the
  *                    call.  1 => longer sequence along the band rows; -1 => as given; 2 => whichever
- *                    takes fewer band steps, ceil(rows / 256) * (columns + 127), except that a pair
- *                    of several bands is never laid out with the longer sequence as columns.  0 => 2.
+ *                    takes fewer band steps, ceil(rows / 256) * (columns + 255), except that a pair
+ *                    of several bands is never laid out with the longer sequence as columns.
+ *                    0 => -1.
  *   small_bits       one-pair-per-lane kernels: 16 => packed 16-bit lanes where provably exact,
  *                    with the 32-bit redo; 32 => 32-bit lanes only.  0 => 16. */
 typedef struct {

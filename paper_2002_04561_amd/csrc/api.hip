@@ -210,10 +210,13 @@ aln_status_t aln_align_batch_ex(const aln_scoring_t* scoring, int64_t n_pairs, c
   }
   const int* list = reinterpret_cast<const int*>(split_ws + L.sp.off_small_idx);
   const int* list_cnt = reinterpret_cast<const int*>(split_ws + L.sp.off_small_cnt);
+  // the redo counter and the group tickets of the 16- and 32-bit launches start at zero
+  int* ticket16 = redo_cnt + 16;
+  int* ticket32 = redo_cnt + 32;
+  hipLaunchKernelGGL(fill_i32_kernel, dim3(1), dim3(64), 0, stream, redo_cnt, 48, 0);
   if (!L.use16)
     return launch_batch_i32(kp, L.bp, q, q_off, s, s_off, tb, out, cigar, cigar_off, workspace, list, list_cnt, 0u,
-                            stream);
-  hipLaunchKernelGGL(fill_i32_kernel, dim3(1), dim3(64), 0, stream, redo_cnt, 1, 0);
+                            ticket32, stream);
   I16Args a;
   a.q = q;
   a.q_off = q_off;
@@ -227,12 +230,13 @@ aln_status_t aln_align_batch_ex(const aln_scoring_t* scoring, int64_t n_pairs, c
   a.idx_count = list_cnt;
   a.redo_idx = redo_idx;
   a.redo_cnt = redo_cnt;
+  a.ticket = ticket16;
   a.force16 = (flags & ALN_FORCE_INT16) ? 1 : 0;
   st = launch_batch_i16(kp, L.bp16, a, tb, stream);
   if (st != ALN_OK) return st;
   // pairs whose 16-bit range was not provably exact, or that saturated, are recomputed in 32 bits
   return launch_batch_i32(kp, L.bp, q, q_off, s, s_off, tb, out, cigar, cigar_off, workspace, redo_idx, redo_cnt,
-                          ALN_RES_INT32_REDO, stream);
+                          ALN_RES_INT32_REDO, ticket32, stream);
 }
 
 // Traceback of one long pair stores 4 bits per cell; beyond this the call is refused.

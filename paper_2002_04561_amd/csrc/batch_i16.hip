@@ -59,13 +59,22 @@ __device__ __forceinline__ bool fits16(const KParams& P, int n, int m) {
   return up <= kBound16 && lo >= -kBound16 && m < 32767;
 }
 
+// Persistent waves take groups of pairs from a device ticket; the groups come in the planner's
+// order (largest shapes first), so the waves drain the list evenly whatever number of them is
+// resident.
+__device__ __forceinline__ int64_t next_group(int* ticket, int lane) {
+  int g = 0;
+  if (lane == 0) g = atomicAdd(ticket, 1);
+  return (int64_t)__shfl(g, 0, 64);
+}
+
 template <int MODE, bool AFFINE, bool TB, int R>
 __global__ __launch_bounds__(kI16Block) void batch_i16_kernel(
     const KParams P, const uint8_t* __restrict__ q, const int64_t* __restrict__ q_off, const uint8_t* __restrict__ s,
     const int64_t* __restrict__ s_off, int64_t n_pairs, int64_t max_n, int64_t max_m, aln_result_t* __restrict__ out,
     uint32_t* __restrict__ cigar, const int64_t* __restrict__ cigar_off, char* __restrict__ ws, size_t slab_bytes,
     size_t rowbuf_bytes, const int* __restrict__ idx, const int* __restrict__ idx_count, int* __restrict__ redo_idx,
-    int* __restrict__ redo_cnt, int force16) {
+    int* __restrict__ redo_cnt, int* __restrict__ ticket, int force16) {
   static_assert(R % 8 == 0 || R == 4, "R must be 4 or a multiple of 8");
   extern __shared__ char smem[];
   int32_t* tab = reinterpret_cast<int32_t*>(smem);
@@ -87,7 +96,6 @@ __global__ __launch_bounds__(kI16Block) void batch_i16_kernel(
   short* __restrict__ profB = prof + (size_t)(64 + lane) * AP * R;
 
   const int64_t wave = (int64_t)blockIdx.x * kI16WavesPerBlock + wib;
-  const int64_t n_waves = (int64_t)gridDim.x * kI16WavesPerBlock;
   char* slab = ws + wave * slab_bytes;
   uint2* __restrict__ rowbuf = reinterpret_cast<uint2*>(slab);
   uint32_t* __restrict__ dirs = reinterpret_cast<uint32_t*>(slab + rowbuf_bytes);
@@ -97,7 +105,7 @@ __global__ __launch_bounds__(kI16Block) void batch_i16_kernel(
   const s2 ge2 = sp(P.ge), goe2 = sp(P.goe), go2 = sp(P.go), one = sp(1), zero = sp(0);
   const s2 neg2 = sp(-32768);
 
-  for (int64_t g = wave; g < groups; g += n_waves) {
+  for (int64_t g = next_group(ticket, lane); g < groups; g = next_group(ticket, lane)) {
     int64_t pp[2];
     int nn[2], mm[2];
     bool act[2], ok16[2], bad[2];
@@ -400,7 +408,7 @@ void launch_i16_t(const KParams& kp, const BatchPlan16& pl, const I16Args& a, hi
   hipLaunchKernelGGL((batch_i16_kernel<MODE, AFFINE, TB, R>), dim3(blocks), dim3(kI16Block), lds, stream, kp, a.q,
                      a.q_off, a.s, a.s_off, pl.n_pairs, pl.max_n, pl.max_m, a.out, a.cigar, a.cigar_off,
                      static_cast<char*>(a.ws), pl.slab_bytes, pl.rowbuf_bytes, a.idx, a.idx_count, a.redo_idx,
-                     a.redo_cnt, a.force16);
+                     a.redo_cnt, a.ticket, a.force16);
 }
 
 template <int MODE, bool AFFINE, bool TB>

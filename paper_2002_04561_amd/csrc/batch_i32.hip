@@ -24,12 +24,22 @@ constexpr int kWavesPerBlock = 4;
 constexpr int kBlock = 64 * kWavesPerBlock;
 constexpr int kWavesPerCU = 8;
 
+// Persistent waves take groups of pairs from a device ticket; the groups come in the planner's
+// order (largest shapes first), so the waves drain the list evenly whatever number of them is
+// resident.
+__device__ __forceinline__ int64_t next_group(int* ticket, int lane) {
+  int g = 0;
+  if (lane == 0) g = atomicAdd(ticket, 1);
+  return (int64_t)__shfl(g, 0, 64);
+}
+
 template <int MODE, bool AFFINE, bool TB>
 __global__ __launch_bounds__(kBlock) void batch_i32_kernel(
     const KParams P, const uint8_t* __restrict__ q, const int64_t* __restrict__ q_off, const uint8_t* __restrict__ s,
     const int64_t* __restrict__ s_off, int64_t n_pairs, int64_t max_n, int64_t max_m, aln_result_t* __restrict__ out,
     uint32_t* __restrict__ cigar, const int64_t* __restrict__ cigar_off, char* __restrict__ ws, size_t slab_bytes,
-    size_t rowbuf_bytes, const int* __restrict__ idx, const int* __restrict__ idx_count, uint32_t extra_flags) {
+    size_t rowbuf_bytes, const int* __restrict__ idx, const int* __restrict__ idx_count, uint32_t extra_flags,
+    int* __restrict__ ticket) {
   __shared__ int32_t tab[kTab * kTab];
   for (int k = threadIdx.x; k < kTab * kTab; k += blockDim.x) {
     const int a = k / kTab, b = k % kTab;
@@ -44,7 +54,6 @@ __global__ __launch_bounds__(kBlock) void batch_i32_kernel(
 
   const int lane = threadIdx.x & 63;
   const int64_t wave = (int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
-  const int64_t n_waves = (int64_t)gridDim.x * kWavesPerBlock;
   char* slab = ws + wave * slab_bytes;
   int2* __restrict__ rowbuf = reinterpret_cast<int2*>(slab);
   uint32_t* __restrict__ dirs = reinterpret_cast<uint32_t*>(slab + rowbuf_bytes);
@@ -53,7 +62,7 @@ __global__ __launch_bounds__(kBlock) void batch_i32_kernel(
   const int64_t groups = (count + 63) / 64;
   const int32_t go = P.go, ge = P.ge, goe = P.goe;
 
-  for (int64_t g = wave; g < groups; g += n_waves) {
+  for (int64_t g = next_group(ticket, lane); g < groups; g = next_group(ticket, lane)) {
     const int64_t slot = g * 64 + lane;
     const bool active = slot < count;
     const int64_t p = active ? (idx ? (int64_t)idx[slot] : slot) : 0;
@@ -252,30 +261,31 @@ __global__ __launch_bounds__(kBlock) void batch_i32_kernel(
 template <int MODE, bool AFFINE, bool TB>
 void launch_one(const KParams& kp, const BatchPlan& pl, const uint8_t* q, const int64_t* q_off, const uint8_t* s,
                 const int64_t* s_off, aln_result_t* out, uint32_t* cigar, const int64_t* cigar_off, void* ws,
-                const int* idx, const int* idx_count, uint32_t extra_flags, hipStream_t stream) {
+                const int* idx, const int* idx_count, uint32_t extra_flags, int* ticket, hipStream_t stream) {
   const size_t slab = pl.rowbuf_bytes + pl.dirs_bytes;
   const int blocks = (pl.n_waves + kWavesPerBlock - 1) / kWavesPerBlock;
   ProfScope prof(TB ? "batch_i32_traceback" : "batch_i32_score", stream);
   hipLaunchKernelGGL((batch_i32_kernel<MODE, AFFINE, TB>), dim3(blocks), dim3(kBlock), 0, stream, kp, q, q_off, s,
                      s_off, pl.n_pairs, pl.max_n, pl.max_m, out, cigar, cigar_off, static_cast<char*>(ws), slab,
-                     pl.rowbuf_bytes, idx, idx_count, extra_flags);
+                     pl.rowbuf_bytes, idx, idx_count, extra_flags, ticket);
 }
 
 template <int MODE>
 void launch_mode(const KParams& kp, const BatchPlan& pl, const uint8_t* q, const int64_t* q_off, const uint8_t* s,
                  const int64_t* s_off, bool tb, aln_result_t* out, uint32_t* cigar, const int64_t* cigar_off,
-                 void* ws, const int* idx, const int* idx_count, uint32_t extra_flags, hipStream_t stream) {
+                 void* ws, const int* idx, const int* idx_count, uint32_t extra_flags, int* ticket,
+                 hipStream_t stream) {
   const bool affine = kp.go != 0;
   if (affine) {
     if (tb)
-      launch_one<MODE, true, true>(kp, pl, q, q_off, s, s_off, out, cigar, cigar_off, ws, idx, idx_count, extra_flags, stream);
+      launch_one<MODE, true, true>(kp, pl, q, q_off, s, s_off, out, cigar, cigar_off, ws, idx, idx_count, extra_flags, ticket, stream);
     else
-      launch_one<MODE, true, false>(kp, pl, q, q_off, s, s_off, out, cigar, cigar_off, ws, idx, idx_count, extra_flags, stream);
+      launch_one<MODE, true, false>(kp, pl, q, q_off, s, s_off, out, cigar, cigar_off, ws, idx, idx_count, extra_flags, ticket, stream);
   } else {
     if (tb)
-      launch_one<MODE, false, true>(kp, pl, q, q_off, s, s_off, out, cigar, cigar_off, ws, idx, idx_count, extra_flags, stream);
+      launch_one<MODE, false, true>(kp, pl, q, q_off, s, s_off, out, cigar, cigar_off, ws, idx, idx_count, extra_flags, ticket, stream);
     else
-      launch_one<MODE, false, false>(kp, pl, q, q_off, s, s_off, out, cigar, cigar_off, ws, idx, idx_count, extra_flags, stream);
+      launch_one<MODE, false, false>(kp, pl, q, q_off, s, s_off, out, cigar, cigar_off, ws, idx, idx_count, extra_flags, ticket, stream);
   }
 }
 
@@ -309,17 +319,17 @@ aln_status_t plan_batch_i32(const KParams& kp, int64_t n_pairs, int64_t max_n, i
 aln_status_t launch_batch_i32(const KParams& kp, const BatchPlan& pl, const uint8_t* q, const int64_t* q_off,
                               const uint8_t* s, const int64_t* s_off, bool tb, aln_result_t* out, uint32_t* cigar,
                               const int64_t* cigar_off, void* ws, const int* idx, const int* idx_count,
-                              uint32_t extra_flags, hipStream_t stream) {
+                              uint32_t extra_flags, int* ticket, hipStream_t stream) {
   if (pl.n_pairs == 0) return ALN_OK;
   switch (kp.mode) {
     case ALN_GLOBAL:
-      launch_mode<ALN_GLOBAL>(kp, pl, q, q_off, s, s_off, tb, out, cigar, cigar_off, ws, idx, idx_count, extra_flags, stream);
+      launch_mode<ALN_GLOBAL>(kp, pl, q, q_off, s, s_off, tb, out, cigar, cigar_off, ws, idx, idx_count, extra_flags, ticket, stream);
       break;
     case ALN_LOCAL:
-      launch_mode<ALN_LOCAL>(kp, pl, q, q_off, s, s_off, tb, out, cigar, cigar_off, ws, idx, idx_count, extra_flags, stream);
+      launch_mode<ALN_LOCAL>(kp, pl, q, q_off, s, s_off, tb, out, cigar, cigar_off, ws, idx, idx_count, extra_flags, ticket, stream);
       break;
     default:
-      launch_mode<ALN_SEMIGLOBAL>(kp, pl, q, q_off, s, s_off, tb, out, cigar, cigar_off, ws, idx, idx_count, extra_flags, stream);
+      launch_mode<ALN_SEMIGLOBAL>(kp, pl, q, q_off, s, s_off, tb, out, cigar, cigar_off, ws, idx, idx_count, extra_flags, ticket, stream);
       break;
   }
   return hipGetLastError() == hipSuccess ? ALN_OK : ALN_E_DEVICE;

@@ -40,9 +40,10 @@ __device__ __forceinline__ int log_bin(int64_t x) {
 }
 
 // Wave-steps the band wavefront spends on a rows x cols problem: one band per 256 rows, each
-// sweeping cols + 63 steps plus a start-up of about 64 steps (ticket, pair lookup, profile).
+// sweeping cols + 63 steps plus about 192 steps of start-up (ticket, pair lookup, profile) and of
+// waiting for the band above to publish its first columns.
 __device__ __forceinline__ int64_t band_steps(int64_t rows, int64_t cols) {
-  return (rows + kWfBand - 1) / kWfBand * (cols + 63 + 64);
+  return (rows + kWfBand - 1) / kWfBand * (cols + 63 + 192);
 }
 
 __global__ void split_reset_kernel(SplitView V) {
@@ -50,24 +51,47 @@ __global__ void split_reset_kernel(SplitView V) {
   if (blockIdx.x == 0 && threadIdx.x < 2) V.counters[threadIdx.x] = 0;
 }
 
-__global__ void split_classify_kernel(int64_t n_pairs, const int64_t* __restrict__ q_off,
-                                      const int64_t* __restrict__ s_off, int64_t max_n, int64_t max_m,
-                                      int64_t big_cells, SplitView V) {
-  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n_pairs;
-       p += (int64_t)gridDim.x * blockDim.x) {
+// Blocks of the classify and scatter passes each own one contiguous chunk of pairs and count its
+// keys in an LDS histogram first, so a batch whose pairs share a few shapes does not serialise on
+// a few global counters.
+constexpr int kPlanThreads = 1024;
+
+__device__ __forceinline__ void chunk_of_block(int64_t n_pairs, int64_t* p0, int64_t* p1) {
+  const int64_t per = (n_pairs + gridDim.x - 1) / gridDim.x;
+  *p0 = (int64_t)blockIdx.x * per;
+  *p1 = *p0 + per < n_pairs ? *p0 + per : n_pairs;
+}
+
+__global__ __launch_bounds__(kPlanThreads) void split_classify_kernel(int64_t n_pairs,
+                                                                      const int64_t* __restrict__ q_off,
+                                                                      const int64_t* __restrict__ s_off,
+                                                                      int64_t max_n, int64_t max_m,
+                                                                      int64_t big_cells, SplitView V) {
+  __shared__ int h[kKeys];
+  __shared__ int n_big;
+  for (int k = threadIdx.x; k < kKeys; k += blockDim.x) h[k] = 0;
+  if (threadIdx.x == 0) n_big = 0;
+  __syncthreads();
+  int64_t p0, p1;
+  chunk_of_block(n_pairs, &p0, &p1);
+  for (int64_t p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
     const int64_t n = q_off[p + 1] - q_off[p], m = s_off[p + 1] - s_off[p];
     const bool fits = n >= 0 && m >= 0 && n <= max_n && m <= max_m;
     int key;
     if (fits && n > 0 && m > 0 && n * m >= big_cells) {
       const int b = log_bin_wide(n * m);
       key = kSmallKeys + (b < kBigKeys ? b : kBigKeys - 1);
-      atomicAdd(&V.counters[1], 1);
+      atomicAdd(&n_big, 1);
     } else {
       key = log_bin(n) * kShapeBins + log_bin(m);
     }
     V.keys[p] = key;
-    atomicAdd(&V.hist[key], 1);
+    atomicAdd(&h[key], 1);
   }
+  __syncthreads();
+  for (int k = threadIdx.x; k < kKeys; k += blockDim.x)
+    if (h[k]) atomicAdd(&V.hist[k], h[k]);
+  if (threadIdx.x == 0 && n_big) atomicAdd(&V.counters[1], n_big);
 }
 
 // One block: turns the key histogram into cursors, largest keys first, and counts the small list.
@@ -99,13 +123,24 @@ __global__ __launch_bounds__(kScanThreads) void sort_scan_kernel(SplitView V) {
 
 // Places every pair at its sorted position: big pairs (positions 0 .. n_big-1) become entries of
 // the wavefront pair table, small ones entries of the inter-sequence list.
-__global__ void sort_scatter_kernel(int64_t n_pairs, const int64_t* __restrict__ q_off,
-                                    const int64_t* __restrict__ s_off, int orient, SplitView V, WfWs W) {
+__global__ __launch_bounds__(kPlanThreads) void sort_scatter_kernel(int64_t n_pairs,
+                                                                    const int64_t* __restrict__ q_off,
+                                                                    const int64_t* __restrict__ s_off, int orient,
+                                                                    SplitView V, WfWs W) {
+  __shared__ int h[kKeys];  // this chunk's count per key, then its next position per key
   const int n_big = V.counters[1];
-  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n_pairs;
-       p += (int64_t)gridDim.x * blockDim.x) {
+  for (int k = threadIdx.x; k < kKeys; k += blockDim.x) h[k] = 0;
+  __syncthreads();
+  int64_t p0, p1;
+  chunk_of_block(n_pairs, &p0, &p1);
+  for (int64_t p = p0 + threadIdx.x; p < p1; p += blockDim.x) atomicAdd(&h[V.keys[p]], 1);
+  __syncthreads();
+  for (int k = threadIdx.x; k < kKeys; k += blockDim.x)
+    if (h[k]) h[k] = atomicAdd(&V.hist[k], h[k]);  // reserve the chunk's range of each key
+  __syncthreads();
+  for (int64_t p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
     const int key = V.keys[p];
-    const int pos = atomicAdd(&V.hist[key], 1);
+    const int pos = atomicAdd(&h[key], 1);
     if (key < kSmallKeys) {
       V.small_idx[pos - n_big] = (int)p;
       continue;
@@ -192,9 +227,9 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 BatchCfg resolve_cfg(const aln_batch_config_t* c) {
   BatchCfg r;
-  r.wf_min_cells = (int64_t)1 << 20;
+  r.wf_min_cells = (int64_t)1 << 16;
   r.wf_waves_per_cu = kWfWavesPerCUDefault;
-  r.orient = 2;
+  r.orient = 0;
   r.small16 = true;
   if (!c) return r;
   if (c->wf_min_cells < 0) r.wf_min_cells = INT64_MAX;
@@ -202,6 +237,7 @@ BatchCfg resolve_cfg(const aln_batch_config_t* c) {
   if (c->wf_waves_per_cu > 0) r.wf_waves_per_cu = c->wf_waves_per_cu;
   if (c->wf_orient < 0) r.orient = 0;
   if (c->wf_orient == 1) r.orient = 1;
+  if (c->wf_orient == 2) r.orient = 2;
   if (c->small_bits == 32) r.small16 = false;
   return r;
 }
@@ -242,12 +278,14 @@ void launch_split(const SplitPlan& sp, int64_t n_pairs, const int64_t* q_off, co
   WfWs W = wf_view(base + sp.wf_base, sp.wf);
   ProfScope prof("plan", stream);
   hipLaunchKernelGGL(split_reset_kernel, dim3(68), dim3(256), 0, stream, V);
-  const int64_t blocks = (n_pairs + 255) / 256;
-  const dim3 grid((unsigned)(blocks < 4096 ? (blocks > 0 ? blocks : 1) : 4096));
-  hipLaunchKernelGGL(split_classify_kernel, grid, dim3(256), 0, stream, n_pairs, q_off, s_off, max_n, max_m,
-                     sp.big_cells, V);
+  // one chunk of at least 4096 pairs per block, at most 512 blocks
+  int64_t blocks = (n_pairs + 4095) / 4096;
+  blocks = blocks < 1 ? 1 : (blocks > 512 ? 512 : blocks);
+  hipLaunchKernelGGL(split_classify_kernel, dim3((unsigned)blocks), dim3(kPlanThreads), 0, stream, n_pairs, q_off,
+                     s_off, max_n, max_m, sp.big_cells, V);
   hipLaunchKernelGGL(sort_scan_kernel, dim3(1), dim3(kScanThreads), 0, stream, V);
-  hipLaunchKernelGGL(sort_scatter_kernel, grid, dim3(256), 0, stream, n_pairs, q_off, s_off, sp.orient, V, W);
+  hipLaunchKernelGGL(sort_scatter_kernel, dim3((unsigned)blocks), dim3(kPlanThreads), 0, stream, n_pairs, q_off,
+                     s_off, sp.orient, V, W);
   hipLaunchKernelGGL(split_scan_kernel, dim3(1), dim3(1024), 0, stream, V, W, sp.item_cap, sp.row_cap, out);
 }
 

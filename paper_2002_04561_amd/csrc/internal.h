@@ -108,7 +108,7 @@ aln_status_t plan_batch_i32(const KParams& kp, int64_t n_pairs, int64_t max_n, i
 aln_status_t launch_batch_i32(const KParams& kp, const BatchPlan& plan, const uint8_t* q, const int64_t* q_off,
                               const uint8_t* s, const int64_t* s_off, bool traceback, aln_result_t* out,
                               uint32_t* cigar, const int64_t* cigar_off, void* ws, const int* idx,
-                              const int* idx_count, uint32_t extra_flags, hipStream_t stream);
+                              const int* idx_count, uint32_t extra_flags, int* ticket, hipStream_t stream);
 
 // batch_i16.hip
 struct BatchPlan16 {
@@ -130,6 +130,7 @@ struct I16Args {
   const int* idx_count;
   int* redo_idx;
   int* redo_cnt;
+  int* ticket;  // group dispenser, zero before the launch
   int force16;
 };
 aln_status_t plan_batch_i16(const KParams& kp, int64_t n_pairs, int64_t max_n, int64_t max_m, bool tb,
@@ -138,7 +139,7 @@ aln_status_t launch_batch_i16(const KParams& kp, const BatchPlan16& plan, const 
                               hipStream_t stream);
 
 // wf_i32.hip
-constexpr int kWfWavesPerCUDefault = 8;
+constexpr int kWfWavesPerCUDefault = 16;
 constexpr int kWfWavesPerCUMax = 32;
 int wf_waves(int per_cu);
 size_t wf_layout(int64_t max_pairs, int64_t max_items, int64_t row_words, int64_t code_words, WfOffsets* o);

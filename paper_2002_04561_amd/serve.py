@@ -119,7 +119,7 @@ class AlignServer:
     """Runs a request stream through aln_align_batch / aln_align_long with continuous batching."""
 
     def __init__(self, scorings: Dict[str, object], budget_bytes: int, streams: int = 3, max_pairs: int = 8192,
-                 device: str = "cuda"):
+                 device: str = "cuda", class_max_pairs: Optional[Dict[str, int]] = None):
         import torch
 
         import paper_2002_04561_amd as aln
@@ -128,9 +128,11 @@ class AlignServer:
         self.adm = Admission(budget_bytes)
         self.streams = [torch.cuda.Stream(device=device) for _ in range(streams)]
         self.max_pairs = max_pairs
+        self.class_max_pairs = dict(class_max_pairs or {})
         self.device = device
         self.completed: List[Completed] = []
         self.cells = 0
+        self.redo = 0  # requests whose 16-bit pass was redone in 32 bits
 
     def _launch(self, batch: List[Request], stream) -> _Flight:
         torch, aln = self.torch, self.aln
@@ -182,6 +184,7 @@ class AlignServer:
         cig = f.cigar.to("cpu").numpy().view(np.uint32) if f.cigar is not None else None
         for k, r in enumerate(f.batch):
             x = res[k]
+            self.redo += int(x["flags"]) & self.aln.RES_INT32_REDO != 0
             tup = (int(x["score"]), int(x["q_begin"]), int(x["q_end"]), int(x["s_begin"]), int(x["s_end"]),
                    int(x["flags"]) & ~self.aln.RES_INT32_REDO)
             runs = None
@@ -214,7 +217,7 @@ class AlignServer:
                     k = self.adm.oldest_class()
                     if k is None:
                         break
-                    batch = self.adm.take_batch(k, self.max_pairs)
+                    batch = self.adm.take_batch(k, self.class_max_pairs.get(k, self.max_pairs))
                     if not batch:
                         break
                     flights[i] = self._launch(batch, self.streams[i])
@@ -225,7 +228,7 @@ class AlignServer:
         wall = time.perf_counter() - t0
         stats = {"requests": len(self.completed), "wall_s": wall, "cells": self.cells,
                  "gcups": self.cells / wall / 1e9, "peak_bytes": self.adm.peak, "budget_bytes": self.adm.budget,
-                 "classes": {}}
+                 "int32_redo": self.redo, "classes": {}}
         by = collections.defaultdict(list)
         for c in self.completed:
             by[c.klass].append(c.latency)

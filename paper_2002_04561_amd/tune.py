@@ -31,7 +31,10 @@ SEARCH = (
     ("wf_orient", (2, 1, -1)),
     ("small_bits", (16, 32)),
 )
-START = dict(wf_min_cells=1 << 20, wf_waves_per_cu=8, wf_orient=2, small_bits=16)
+START = dict(wf_min_cells=1 << 16, wf_waves_per_cu=16, wf_orient=-1, small_bits=16)
+# One lane runs a pair's whole matrix in the one-pair-per-lane kernels: thresholds that would leave
+# pairs above this many cells there are not tried (a single such pair takes tens of milliseconds).
+LANE_CELLS_MAX = 1 << 22
 CUTOFF = 1.5  # a candidate whose first run is this much slower than the best is not timed again
 
 _CACHE: Dict[str, dict] = {}
@@ -100,8 +103,12 @@ def tune(ba, stream=None, repeats: int = 1, log=None, cache_file: Optional[str] 
 
     ba.run(stream)  # first call of the process: module load and allocator warm-up
     best_ms = measure(cur)
+    max_cells = int(np.max((qo[1:] - qo[:-1]) * (so[1:] - so[:-1]))) if len(qo) > 1 else 0
     for field, values in SEARCH:
         for v in values:
+            if field == "wf_min_cells" and max_cells > LANE_CELLS_MAX and not (0 < v <= LANE_CELLS_MAX) \
+                    and not (ba.flags & 1):
+                continue
             cand = BatchConfig(**{**asdict(cur), field: v})
             ms = measure(cand)
             if ms < best_ms:

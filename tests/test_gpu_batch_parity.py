@@ -106,7 +106,7 @@ def test_uneven_split_score_only(gpu, mode, scheme):
     w = synth.Workload("uneven", mode, A, go, ge, q, qo, s, so, match=ma, mismatch=mi, subst=sub)
     n, m = w.lengths()
     assert np.any(n * m >= (1 << 20)) and np.any(n * m < (1 << 20))
-    gres, _ = run_gpu(w, aln.SCORE_ONLY)
+    gres, _ = run_gpu(w, aln.SCORE_ONLY, config=aln.BatchConfig(wf_min_cells=1 << 20))
     ores, _ = run_oracle(w, False)
     bad = compare(w, gres, None, ores, None, "uneven")
     assert not bad, "\n".join(bad[:10])
@@ -135,9 +135,10 @@ def test_overflow_redo(gpu, mode, tb):
     s, so = synth.pack(ss)
     w = synth.Workload("overflow", mode, 4, -30, -20, q, qo, s, so, match=120, mismatch=-40)
     ores, ocig = run_oracle(w, tb)
+    lanes_only = aln.BatchConfig(wf_min_cells=-1)  # every pair on the one-pair-per-lane kernels
     for extra in (0, aln.FORCE_INT16):
         flags = (aln.TRACEBACK if tb else aln.SCORE_ONLY) | extra
-        gres, gcig = run_gpu(w, flags)
+        gres, gcig = run_gpu(w, flags, config=lanes_only)
         bad = compare(w, gres, gcig, ores, ocig, "overflow")
         assert not bad, "\n".join(bad[:10])
         redo = (gres["flags"] & aln.RES_INT32_REDO) != 0
