@@ -146,13 +146,19 @@ aln_status_t aln_align_batch(const aln_scoring_t* scoring, int64_t n_pairs, cons
  *                    of several bands is never laid out with the longer sequence as columns.
  *                    0 => -1.
  *   small_bits       one-pair-per-lane kernels: 16 => packed 16-bit lanes where provably exact,
- *                    with the 32-bit redo; 32 => 32-bit lanes only.  0 => 16. */
+ *                    with the 32-bit redo; 32 => 32-bit lanes only.  0 => 16.
+ *   wf_group         wavefront engine: 1 => every band on its own wave, hand-offs through HBM;
+ *                    4 => workgroups of 4 consecutive bands handing rows over in LDS, with a courier
+ *                    wave for the hand-offs to and from other workgroups.  0 => 4 when the batch has
+ *                    fewer than 16 bands per compute unit (estimated from total_q + total_s), else 1.
+ *                    aln_align_long always uses 4. */
 typedef struct {
   int64_t wf_min_cells;
   int32_t wf_waves_per_cu;
   int32_t wf_orient;
   int32_t small_bits;
-  int32_t reserved[3]; /* must be zero */
+  int32_t wf_group;
+  int32_t reserved[2]; /* must be zero */
 } aln_batch_config_t;
 
 /* aln_align_batch with explicit execution choices; config == NULL is aln_align_batch.  The

@@ -46,6 +46,15 @@ __device__ __forceinline__ int64_t band_steps(int64_t rows, int64_t cols) {
   return (rows + kWfBand - 1) / kWfBand * (cols + 63 + 192);
 }
 
+// Whether a wavefront pair runs transposed.  Row slots (2 (columns + 1) entries) are reserved from
+// the subject total, so a pair of two or more bands may only be flipped to shorter columns; a
+// one-band pair needs no slots.
+__device__ __forceinline__ bool orient_flip(int64_t n, int64_t m, int orient) {
+  if (orient == 1) return m > n;
+  if (orient == 2) return band_steps(m, n) < band_steps(n, m) && (n <= m || m <= kWfBand);
+  return false;
+}
+
 __global__ void split_reset_kernel(SplitView V) {
   for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < kKeys; k += gridDim.x * blockDim.x) V.hist[k] = 0;
   if (blockIdx.x == 0 && threadIdx.x < 2) V.counters[threadIdx.x] = 0;
@@ -66,7 +75,7 @@ __global__ __launch_bounds__(kPlanThreads) void split_classify_kernel(int64_t n_
                                                                       const int64_t* __restrict__ q_off,
                                                                       const int64_t* __restrict__ s_off,
                                                                       int64_t max_n, int64_t max_m,
-                                                                      int64_t big_cells, SplitView V) {
+                                                                      int64_t big_cells, int orient, SplitView V) {
   __shared__ int h[kKeys];
   __shared__ int n_big;
   for (int k = threadIdx.x; k < kKeys; k += blockDim.x) h[k] = 0;
@@ -79,7 +88,11 @@ __global__ __launch_bounds__(kPlanThreads) void split_classify_kernel(int64_t n_
     const bool fits = n >= 0 && m >= 0 && n <= max_n && m <= max_m;
     int key;
     if (fits && n > 0 && m > 0 && n * m >= big_cells) {
-      const int b = log_bin_wide(n * m);
+      // wavefront pairs by band work, bands x (columns + 63), largest first: a workgroup relaxes
+      // kWfWavesPerBlock consecutive bands, which then take about the same time
+      const bool flip = orient_flip(n, m, orient);
+      const int64_t rows = flip ? m : n, cols = flip ? n : m;
+      const int b = log_bin_wide((rows + kWfBand - 1) / kWfBand * (cols + 63));
       key = kSmallKeys + (b < kBigKeys ? b : kBigKeys - 1);
       atomicAdd(&n_big, 1);
     } else {
@@ -147,11 +160,7 @@ __global__ __launch_bounds__(kPlanThreads) void sort_scatter_kernel(int64_t n_pa
     }
     const int64_t qb = q_off[p], sb = s_off[p];
     const int32_t n = (int32_t)(q_off[p + 1] - qb), m = (int32_t)(s_off[p + 1] - sb);
-    // Row slots (2 (columns + 1) entries) are reserved from the subject total, so a pair of two or
-    // more bands may only be flipped to shorter columns; a one-band pair needs no slots.
-    bool flip = false;
-    if (orient == 1) flip = m > n;
-    if (orient == 2) flip = band_steps(m, n) < band_steps(n, m) && (n <= m || m <= kWfBand);
+    const bool flip = orient_flip(n, m, orient);
     WfPair pr;
     pr.q_off = flip ? sb : qb;
     pr.s_off = flip ? qb : sb;
@@ -228,6 +237,7 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 BatchCfg resolve_cfg(const aln_batch_config_t* c) {
   BatchCfg r;
   r.wf_min_cells = (int64_t)1 << 16;
+  r.wf_group = 0;
   r.wf_waves_per_cu = kWfWavesPerCUDefault;
   r.orient = 0;
   r.small16 = true;
@@ -235,6 +245,7 @@ BatchCfg resolve_cfg(const aln_batch_config_t* c) {
   if (c->wf_min_cells < 0) r.wf_min_cells = INT64_MAX;
   if (c->wf_min_cells > 0) r.wf_min_cells = c->wf_min_cells;
   if (c->wf_waves_per_cu > 0) r.wf_waves_per_cu = c->wf_waves_per_cu;
+  if (c->wf_group > 0) r.wf_group = c->wf_group;
   if (c->wf_orient < 0) r.orient = 0;
   if (c->wf_orient == 1) r.orient = 1;
   if (c->wf_orient == 2) r.orient = 2;
@@ -264,6 +275,12 @@ aln_status_t plan_split(int64_t n_pairs, int64_t total_q, int64_t total_s, bool 
   off += wf_layout(n_pairs + 1, max_items, sp->row_cap, 0, &sp->wf);
   sp->total_bytes = off;
   sp->wf_waves = wf_waves(cfg.wf_waves_per_cu);
+  // Groups of bands pay off when the batch has few bands per SIMD: then each compute wave is alone
+  // on its SIMD and nothing hides its device-memory waits.  Bands are estimated from the letters
+  // (rows along the longer sequence, 256 per band).
+  const int cus = device_cu_count();
+  const int64_t est_bands = (total_q + total_s) / (2 * kWfBand);
+  sp->grouped = cfg.wf_group == 4 || (cfg.wf_group == 0 && est_bands < (int64_t)16 * (cus > 0 ? cus : 1));
   return sp->wf_waves > 0 ? ALN_OK : ALN_E_DEVICE;
 }
 
@@ -282,7 +299,7 @@ void launch_split(const SplitPlan& sp, int64_t n_pairs, const int64_t* q_off, co
   int64_t blocks = (n_pairs + 4095) / 4096;
   blocks = blocks < 1 ? 1 : (blocks > 512 ? 512 : blocks);
   hipLaunchKernelGGL(split_classify_kernel, dim3((unsigned)blocks), dim3(kPlanThreads), 0, stream, n_pairs, q_off,
-                     s_off, max_n, max_m, sp.big_cells, V);
+                     s_off, max_n, max_m, sp.big_cells, sp.orient, V);
   hipLaunchKernelGGL(sort_scan_kernel, dim3(1), dim3(kScanThreads), 0, stream, V);
   hipLaunchKernelGGL(sort_scatter_kernel, dim3((unsigned)blocks), dim3(kPlanThreads), 0, stream, n_pairs, q_off,
                      s_off, sp.orient, V, W);

@@ -144,8 +144,10 @@ constexpr int kWfWavesPerCUMax = 32;
 int wf_waves(int per_cu);
 size_t wf_layout(int64_t max_pairs, int64_t max_items, int64_t row_words, int64_t code_words, WfOffsets* o);
 WfWs wf_view(void* base, const WfOffsets& o);
+// grouped: workgroups of 4 consecutive bands with LDS hand-offs and a courier wave for HBM
 aln_status_t launch_wf_i32(const KParams& kp, const WfWs& W, const uint8_t* q, const uint8_t* s, aln_result_t* out,
-                           int max_waves, bool tb, uint32_t* cigar, int64_t cigar_cap, hipStream_t stream);
+                           int max_waves, bool grouped, bool tb, uint32_t* cigar, int64_t cigar_cap,
+                           hipStream_t stream);
 aln_status_t plan_long(int64_t n, int64_t m, bool tb, LongPlan* plan);
 aln_status_t launch_long(const KParams& kp, const LongPlan& plan, const uint8_t* q, int64_t n, const uint8_t* s,
                          int64_t m, aln_result_t* out, uint32_t* cigar, int64_t cigar_cap, void* ws,
@@ -156,6 +158,7 @@ struct SplitPlan {
   int64_t big_cells;  // pairs with n*m >= big_cells go to the wavefront engine
   int orient;         // wavefront pair orientation: 1 longer sequence along the rows, 0 as given, 2 cheaper
   int64_t item_cap, row_cap;  // bands and row-slot entries the workspace holds
+  bool grouped;               // the wavefront engine runs workgroups of 4 consecutive bands
   WfOffsets wf;
   size_t off_small_idx, off_small_cnt, off_keys, off_hist, wf_base, total_bytes;
   int wf_waves;
@@ -163,6 +166,7 @@ struct SplitPlan {
 // Resolved execution choices of a batch call (defaults filled in).
 struct BatchCfg {
   int64_t wf_min_cells;
+  int wf_group;  // 0: by the batch's size, 1: bands on their own, 4: groups of 4 bands
   int wf_waves_per_cu;
   int orient;  // 1 longer along the rows, 0 as given, 2 the cheaper of the two
   bool small16;

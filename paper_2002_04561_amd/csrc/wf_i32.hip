@@ -1,26 +1,24 @@
 // Intra-sequence wavefront engine, 32-bit lanes: bands of rows relaxed as anti-diagonal fronts.
 //
-// A work item is one band (BH = 64*R rows) of one pair.  A wave relaxes a band:
-// lane l owns R consecutive rows and works on column j = t - l + 1 at step t,
-// so the 64 lanes sweep the band as an anti-diagonal front (cells on one
-// anti-diagonal are independent, AnySeq Sec. III-A).  The lane above hands its
-// bottom-row H and E (and the subject letter) down with a DPP wave_shr:1 move
-// each step; lane 0 reads the band's top row, lane 63 emits the band's bottom
-// row through a DPP wave_shl:1 shift register that is stored every 64 steps.
+// A work item is one band (BH = 64*R rows) of one pair.  A wave relaxes a band: lane l owns R
+// consecutive rows and works on column j = t - l + 1 at step t, so the 64 lanes sweep the band as an
+// anti-diagonal front (cells on one anti-diagonal are independent, AnySeq Sec. III-A).  The lane
+// above hands its bottom-row H and E (and the subject letter) down with a DPP wave_shr:1 move each
+// step; lane 0 reads the band's top row from an LDS stage refilled every kBlk steps, and lane 63's
+// outputs collect in a DPP wave_shl:1 shift register that is written out every kBlk steps.
 //
-// Items are handed out in order from one atomic ticket to persistent waves, so
-// several pairs of different sizes share the device the way the paper's
-// dynamic wavefront shares its queue between alignments (Sec. IV-A).  A band's
-// bottom row goes to one of two row slots of its pair in HBM; a per-item
-// progress counter, stored once the row data it covers has completed (all
-// cross-wave data and counters use device-coherent sc1 accesses), tells the
-// next band how many columns are ready (the tile border publication of
-// Sec. IV-B, with counters instead of one kernel launch per tile diagonal).  Two slots suffice: band
-// b+2 can only write column c after band b+1 has consumed column c of the
-// slot, by the chain of dependencies.  Band b+1 is only handed out after band
-// b, so every wait is on a band that is already running; every wait is also
-// bounded -- a wave that spins too long raises an error flag and leaves, so
-// the grid always drains.
+// Work is handed out in groups of kWfWavesPerBlock consecutive items from one atomic ticket, so
+// several pairs of different sizes share the device the way the paper's dynamic wavefront shares
+// its queue between alignments (Sec. IV-A).  A workgroup relaxes one group: its compute waves take
+// the group's bands, and the band below of a pair reads the band above's bottom row from an LDS ring
+// with LDS progress counters -- the tile border publication of Sec. IV-B, without device memory.
+// Where a pair continues into the next group, the workgroup's courier wave copies the last band's
+// row to the pair's row slot in HBM and publishes a per-band progress counter once the stores have
+// completed (device-coherent sc1 accesses); the next group's courier streams it into its first
+// band's ring.  Only couriers wait on device memory, so the compute waves run at the rate of the
+// recurrence.  Groups are handed out in order, so every group a courier waits on is already running;
+// every wait is bounded -- a wave that waits too long raises an error flag and leaves its band, and
+// all waves still meet at the group's barriers, so the grid always drains.
 #include <type_traits>
 
 #include "internal.h"
@@ -29,9 +27,17 @@
 namespace mialign {
 namespace {
 
-constexpr int kWfWavesPerBlock = 4;
-constexpr int kWfBlock = 64 * kWfWavesPerBlock;
-constexpr long long kSpinLimit = 1ll << 22;
+// A workgroup is a group of kWfWavesPerBlock compute waves, which relax consecutive bands, plus one
+// courier wave.  Consecutive bands of a pair hand their rows to each other through LDS rings; the
+// courier streams the group's first input row from HBM and its last output row to HBM, so only the
+// courier ever waits on device memory.
+constexpr int kWfWavesPerBlock = 4;                   // compute waves (bands) per workgroup
+constexpr int kWfBlock = 64 * (kWfWavesPerBlock + 1);  // plus the courier
+constexpr int kRing = 256;                            // columns held by one LDS ring
+constexpr int kBlkGrouped = 32;                       // steps between lane-0 input refills, grouped
+constexpr int kWfBlockAlone = 64 * kWfWavesPerBlock;  // bands on their own: no courier
+constexpr long long kSpinLimit = 1ll << 22;           // polls of device memory before giving up
+constexpr long long kLdsSpinLimit = 1ll << 26;        // polls of LDS before giving up
 
 // Where a band's substitution scores sigma(row letter, column letter) - ge come from:
 //   kProfTable  a 32-bit LDS table indexed by both letters (any score range);
@@ -54,13 +60,15 @@ __device__ __forceinline__ bool better(int s1, int i1, int j1, int s2, int i2, i
   return s1 > s2 || (s1 == s2 && (i1 < i2 || (i1 == i2 && j1 < j2)));
 }
 
+// Bands on their own (one wave per band, hand-offs through HBM).
+//
 // Values are kept with a row bias: Hb(i,j) = H(i,j) - i*ge, and likewise E and F.  Then
 //   Eb(i,j) = max(Eb(i-1,j), Hb(i-1,j) + go)          (extension costs nothing: one add less)
 //   Fb(i,j) = max(Fb(i,j-1) + ge, Hb(i,j-1) + go + ge)
 //   Hb(i,j) = max(Hb(i-1,j-1) + sigma - ge, Eb, Fb [, -i*ge for local])
 // which is Eqs. (1), (4), (5) with every term shifted by the same per-row constant.
 template <int MODE, bool AFFINE, int PROF, bool TB, int R>
-__global__ __launch_bounds__(kWfBlock) void wf_i32_kernel(const KParams P, const uint8_t* __restrict__ Q,
+__global__ __launch_bounds__(kWfBlockAlone) void wf_i32_kernel(const KParams P, const uint8_t* __restrict__ Q,
                                                           const uint8_t* __restrict__ S, WfWs W) {
   static_assert(PROF != kProfLane || R == 4, "a lane profile word holds 4 rows");
   // sigma - ge by (query letter, subject letter); also the source of the byte profiles
@@ -385,6 +393,448 @@ __global__ __launch_bounds__(kWfBlock) void wf_i32_kernel(const KParams P, const
   }
 }
 
+// Bands in groups (workgroups of kWfWavesPerBlock bands and a courier), same recurrence.
+// Values are kept with a row bias: Hb(i,j) = H(i,j) - i*ge, and likewise E and F.  Then
+//   Eb(i,j) = max(Eb(i-1,j), Hb(i-1,j) + go)          (extension costs nothing: one add less)
+//   Fb(i,j) = max(Fb(i,j-1) + ge, Hb(i,j-1) + go + ge)
+//   Hb(i,j) = max(Hb(i-1,j-1) + sigma - ge, Eb, Fb [, -i*ge for local])
+// which is Eqs. (1), (4), (5) with every term shifted by the same per-row constant.
+template <int MODE, bool AFFINE, int PROF, bool TB, int R>
+__global__ __launch_bounds__(kWfBlock) void wf_i32_group_kernel(const KParams P, const uint8_t* __restrict__ Q,
+                                                          const uint8_t* __restrict__ S, WfWs W) {
+  static_assert(PROF != kProfLane || R == 4, "a lane profile word holds 4 rows");
+  // sigma - ge by (query letter, subject letter); also the source of the byte profiles
+  __shared__ int32_t tab[kTab * kTab];
+  constexpr int BLK = kBlkGrouped;
+  __shared__ int4 stage[kWfWavesPerBlock][3][BLK / 4];  // lane-0 inputs of BLK steps: H, E, letter
+  // ring k carries the rows feeding compute wave k; ring kWfWavesPerBlock feeds the courier
+  __shared__ int2 ring[kWfWavesPerBlock + 1][kRing];
+  __shared__ int pub[kWfWavesPerBlock + 1];  // columns written into each ring
+  __shared__ int con[kWfWavesPerBlock + 1];  // columns read out of each ring
+  __shared__ long long s_t0;                 // first item of the group
+  __shared__ int s_err;
+  extern __shared__ uint32_t lprof[];        // kProfLane: [wave][letter][lane], alphabet letters
+  for (int k = threadIdx.x; k < kTab * kTab; k += blockDim.x) {
+    const int a = k / kTab, b = k % kTab;
+    tab[k] = (a >= P.alphabet || b >= P.alphabet) ? -kBig32 : (int32_t)P.sig[a * kMaxAlphabet + b] - P.ge;
+  }
+  __syncthreads();
+  constexpr int BH = 64 * R;
+  const int lane = threadIdx.x & 63;
+  const int wib = threadIdx.x >> 6;
+  const int cw = wib < kWfWavesPerBlock ? wib : 0;  // the courier borrows wave 0's stage pointers
+  int* st_h = reinterpret_cast<int*>(&stage[cw][0][0]);
+  int* st_e = reinterpret_cast<int*>(&stage[cw][1][0]);
+  int* st_c = reinterpret_cast<int*>(&stage[cw][2][0]);
+  const int32_t go = P.go, ge = P.ge, goe = P.goe;
+  const int np = *W.n_pairs;
+  const int64_t n_items = *W.n_items;
+
+  // Bounded waits.  A wave that gives up raises the group's and the launch's error flags and leaves
+  // its band; every wave still meets the group's barriers, so the grid drains.
+  auto give_up = [&]() {
+    if (lane == 0) {
+      __hip_atomic_store(&s_err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      __hip_atomic_store(W.error, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  };
+  auto lds_wait_ge = [&](int* p, int v) -> bool {
+    long long spins = 0;
+    while (__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) < v) {
+      __builtin_amdgcn_s_sleep(1);
+      if (++spins > kLdsSpinLimit || __hip_atomic_load(&s_err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) {
+        give_up();
+        return false;
+      }
+    }
+    return true;
+  };
+
+  // The courier: for the group's first band (if it has a band above, in another group) it streams
+  // that band's bottom row from HBM into ring 0, 64 columns at a time, once the band above has
+  // published them; for the group's last band (if its band below is in another group) it copies
+  // ring kWfWavesPerBlock to the pair's row slot in HBM and publishes the band's progress counter
+  // once those stores have completed.  HBM rows and counters use device-coherent (sc1) accesses.
+  auto courier = [&](int64_t t0) {
+    const int64_t tin = t0, tout = t0 + kWfWavesPerBlock - 1;
+    bool in_on = false, out_on = false;
+    int m_in = 0, m_out = 0;
+    const int2* src = nullptr;
+    int2* dst = nullptr;
+    if (tin < n_items) {
+      const WfPair a = W.pairs[np == 1 ? 0 : W.item_pair[tin]];
+      const int b = (int)(tin - a.item0);
+      if (b > 0) {
+        in_on = true;
+        m_in = a.m;
+        src = W.rows + a.row_off + (int64_t)((b + 1) & 1) * ((int64_t)a.m + 1);
+      }
+    }
+    if (tout < n_items) {
+      const WfPair a = W.pairs[np == 1 ? 0 : W.item_pair[tout]];
+      const int b = (int)(tout - a.item0);
+      if (b + 1 < a.nb) {
+        out_on = true;
+        m_out = a.m;
+        dst = W.rows + a.row_off + (int64_t)(b & 1) * ((int64_t)a.m + 1);
+      }
+    }
+    int in_done = 0, out_done = 0, seen = 0;
+    long long idle = 0;
+    while ((in_on && in_done < m_in) || (out_on && out_done < m_out)) {
+      bool moved = false;
+      if (in_on && in_done < m_in) {
+        const int want = min(in_done + 64, m_in);
+        if (seen < want) seen = __hip_atomic_load(W.flags + (tin - 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (seen >= want &&
+            __hip_atomic_load(&con[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) >= want - kRing) {
+          // the row loads are issued after the counter load has returned (device-coherent loads)
+          const int col = in_done + 1 + lane;
+          if (col <= want) {
+            const long long v = __hip_atomic_load(reinterpret_cast<const long long*>(src + col), __ATOMIC_RELAXED,
+                                                  __HIP_MEMORY_SCOPE_AGENT);
+            ring[0][col % kRing] = make_int2((int32_t)(v & 0xffffffffll), (int32_t)(v >> 32));
+          }
+          asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+          if (lane == 0) __hip_atomic_store(&pub[0], want, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+          in_done = want;
+          moved = true;
+        }
+      }
+      if (out_on && out_done < m_out) {
+        const int want = min(out_done + 64, m_out);
+        if (__hip_atomic_load(&pub[kWfWavesPerBlock], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) >= want) {
+          const int col = out_done + 1 + lane;
+          if (col <= want) {
+            const int2 v = ring[kWfWavesPerBlock][col % kRing];
+            const long long pv = ((long long)(uint32_t)v.x) | ((long long)v.y << 32);
+            __hip_atomic_store(reinterpret_cast<long long*>(dst + col), pv, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+          }
+          // stores complete (device-coherent) before the counter that announces them; the ring
+          // values were read before the stores were issued, so the slots can be released too
+          asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)" ::: "memory");
+          if (lane == 0) {
+            __hip_atomic_store(W.flags + tout, want, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&con[kWfWavesPerBlock], want, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+          }
+          out_done = want;
+          moved = true;
+        }
+      }
+      if (moved) {
+        idle = 0;
+      } else {
+        __builtin_amdgcn_s_sleep(1);
+        if (++idle > kSpinLimit || __hip_atomic_load(&s_err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) ||
+            __hip_atomic_load(W.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+          give_up();
+          break;
+        }
+      }
+    }
+  };
+
+  for (;;) {
+    if (threadIdx.x == 0) {
+      s_t0 = (int64_t)atomicAdd(reinterpret_cast<unsigned long long*>(W.ticket), (unsigned long long)kWfWavesPerBlock);
+      for (int k = 0; k <= kWfWavesPerBlock; ++k) {
+        pub[k] = 0;
+        con[k] = 0;
+      }
+      s_err = 0;
+    }
+    __syncthreads();
+    const int64_t t0g = s_t0;
+    if (t0g >= n_items) break;  // the same for the whole workgroup
+    const bool launch_err = __hip_atomic_load(W.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+    if (!launch_err && wib == kWfWavesPerBlock) {
+      courier(t0g);
+    } else if (!launch_err && t0g + wib < n_items) {
+    const int64_t t = t0g + wib;
+    const WfPair pr = W.pairs[np == 1 ? 0 : W.item_pair[t]];
+    const int b = (int)(t - pr.item0);
+    const int n = pr.n, m = pr.m, nb = pr.nb;
+    // rows come from the query array, columns from the subject array, or the reverse when flipped
+    const bool flip = pr.flip != 0;
+    const uint8_t* __restrict__ q = (flip ? S : Q) + pr.q_off;
+    const uint8_t* __restrict__ s = (flip ? Q : S) + pr.s_off;
+    // sigma - ge of a (row letter, column letter) pair, taken in the call's (query, subject) order
+    auto sig_rc = [&](int cr, int cc) -> int { return flip ? tab[cc * kTab + cr] : tab[cr * kTab + cc]; };
+
+    const int i0 = b * BH;
+    int prof[R];  // kProfReg: 4 bytes sigma - ge against letters 0..3; kProfTable: table offset of the letter
+    int32_t hl[R], f[R], bv[R], nu[R];
+    int bj[R];
+    int rowc[R];
+    bool bad = false;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int i = i0 + lane * R + r + 1;
+      int c = kPad;
+      if (i <= n) {
+        c = q[i - 1];
+        if (c >= P.alphabet) {
+          bad = true;
+          c = kPad;
+        }
+      }
+      rowc[r] = c;
+      if (PROF == kProfReg) {
+        uint32_t w = 0;
+        for (int a = 0; a < 4; ++a) {
+          const int v = (c < P.alphabet && a < P.alphabet) ? sig_rc(c, a) : -128;
+          w |= ((uint32_t)(v & 0xff)) << (8 * a);
+        }
+        prof[r] = (int)w;
+      } else if (PROF == kProfTable) {
+        prof[r] = flip ? c : c * kTab;  // the table is indexed [query letter][subject letter]
+      } else {
+        prof[r] = 0;
+      }
+      hl[r] = (MODE == ALN_GLOBAL) ? go : -i * ge;  // Hb(i, 0)
+      f[r] = kNeg32;
+      nu[r] = -i * ge;                                // local floor: H = 0
+      bv[r] = kNeg32;
+      bj[r] = 0;
+    }
+    uint32_t* __restrict__ lp = lprof + (PROF == kProfLane ? wib * P.alphabet * 64 + lane : 0);
+    if (PROF == kProfLane) {
+      // this lane's word per column letter; each lane reads only its own words, so no barrier
+      for (int a = 0; a < P.alphabet; ++a) {
+        uint32_t w = 0;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const int v = rowc[r] < P.alphabet ? sig_rc(rowc[r], a) : -128;
+          w |= ((uint32_t)(v & 0xff)) << (8 * r);
+        }
+        lp[a * 64] = w;
+      }
+    }
+    const int irow0 = i0 + lane * R;  // the row just above this lane's first row
+    int32_t diag = (MODE == ALN_GLOBAL) ? (irow0 > 0 ? go : 0) : -irow0 * ge;  // Hb(irow0, 0)
+    uint16_t* __restrict__ codes = TB ? W.codes + pr.code_off + (size_t)(b * 64 + lane) * (size_t)m : nullptr;
+    int32_t bot_h = 0, bot_e = kNeg32, cur_c = 0, out_h = 0, out_e = 0;
+    // semi-global: the band holding row n tracks row n's running maximum
+    const bool last_band = (b == nb - 1);
+    int32_t brow = -n * ge;  // Hb(n, 0), i.e. H(n, 0) = 0
+    int browj = 0;
+    const int rn = n - 1 - irow0;  // index of row n among this lane's rows
+
+    bool failed = false;
+    int2* __restrict__ rin = ring[wib];       // rows of the band above (b > 0)
+    int2* __restrict__ rout = ring[wib + 1];  // this band's bottom row, for the band below
+    const bool has_out = b + 1 < nb;
+    // subject letter of column col as the profile kind indexes it (0 past the end)
+    auto letter = [&](int col) -> int {
+      int c = 0;
+      if (col <= m) {
+        c = s[col - 1];
+        if (c >= P.alphabet) {
+          bad = true;
+          c = PROF == kProfTable ? kPad : 0;
+        }
+        if (PROF == kProfReg) c *= 8;
+        if (PROF == kProfLane) c *= 64;
+        if (PROF == kProfTable && flip) c *= kTab;
+      }
+      return c;
+    };
+    int c_next = lane < BLK ? letter(1 + lane) : 0;  // prefetched one block ahead
+
+    const int steps = m + 63;
+    for (int tb = 0; tb < steps; tb += BLK) {
+      // lane-0 inputs for steps tb..tb+BLK-1 (columns tb+1..tb+BLK), held by lanes < BLK
+      const int col_in = tb + 1 + lane;
+      const int sreg = c_next;
+      c_next = lane < BLK ? letter(col_in + BLK) : 0;
+      int32_t th = 0, te = kNeg32;
+      if (b == 0) {
+        th = (MODE == ALN_GLOBAL) ? go + col_in * ge : 0;
+      } else {
+        const int need = min(tb + BLK, m);
+        if (!lds_wait_ge(&pub[wib], need)) {
+          failed = true;
+          break;
+        }
+        if (lane < BLK && col_in <= m) {
+          const int2 v = rin[col_in % kRing];
+          th = v.x;
+          te = v.y;
+        }
+        // the ring reads are complete before their slots are released to the band above
+        asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+        if (lane == 0) __hip_atomic_store(&con[wib], need, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      }
+      if (lane < BLK) {
+        st_h[lane] = th;
+        st_e[lane] = te;
+        st_c[lane] = sreg;
+      }
+      // One step: lane l relaxes column j = t - l + 1 for its R rows.
+      auto step = [&](int t, int in_top_h, int in_top_e, int in_top_c, auto checked, int32_t* hk) {
+        const int j = t - lane + 1;
+        const int in_h = dpp_shr1(in_top_h, bot_h);
+        const int in_e = dpp_shr1(in_top_e, bot_e);
+        const int in_c = dpp_shr1(in_top_c, cur_c);
+        cur_c = in_c;
+        if (!decltype(checked)::value || (j >= 1 && j <= m)) {
+          int32_t hd = diag, hup = in_h, eup = in_e;
+          int32_t hn = 0;
+          uint32_t word = 0;
+          const int pw = PROF == kProfLane ? (int)lp[in_c] : 0;
+#pragma unroll
+          for (int r = 0; r < R; ++r) {
+            const int32_t hlo = hl[r];
+            const int32_t e = AFFINE ? max(eup, hup + go) : hup;
+            const int32_t ff = AFFINE ? max(f[r] + ge, hlo + goe) : hlo + ge;
+            const int32_t sg = PROF == kProfReg    ? __builtin_amdgcn_sbfe(prof[r], in_c, 8)
+                               : PROF == kProfLane ? __builtin_amdgcn_sbfe(pw, 8 * r, 8)
+                                                   : tab[prof[r] + in_c];
+            const int32_t d = hd + sg;
+            int32_t h = max(d, max(e, ff));
+            if (MODE == ALN_LOCAL) h = max(h, nu[r]);
+            if (TB) {
+              uint32_t src = (d == h) ? 0u : ((e == h) ? 1u : 2u);
+              if (MODE == ALN_LOCAL && h == nu[r]) src = 3u;
+              const uint32_t xe = AFFINE ? (uint32_t)(hup + go != e) : 0u;
+              const uint32_t xf = AFFINE ? (uint32_t)(hlo + goe != ff) : 0u;
+              word |= (src | (xe << 2) | (xf << 3)) << (4 * r);
+            }
+            if (MODE == ALN_LOCAL) {
+              if (decltype(checked)::value) {
+                if (h > bv[r]) {
+                  bv[r] = h;
+                  bj[r] = j;
+                }
+              } else {
+                hk[r] = h;
+              }
+            }
+            if (MODE == ALN_SEMIGLOBAL && r == rn) hn = h;
+            f[r] = ff;
+            hl[r] = h;
+            hd = hlo;
+            hup = h;
+            eup = e;
+          }
+          if (TB) codes[j - 1] = (uint16_t)word;
+          if (MODE == ALN_SEMIGLOBAL && last_band && rn >= 0 && rn < R && hn > brow) {
+            brow = hn;
+            browj = j;
+          }
+          bot_h = hup;
+          bot_e = eup;
+          diag = in_h;
+        }
+        out_h = dpp_shl1(bot_h, out_h);
+        out_e = dpp_shl1(bot_e, out_e);
+      };
+      for (int g4 = 0; g4 < BLK / 4; ++g4) {
+        const int t0 = tb + 4 * g4;
+        const int4 vh = reinterpret_cast<const int4*>(st_h)[g4];
+        const int4 ve = reinterpret_cast<const int4*>(st_e)[g4];
+        const int4 vc = reinterpret_cast<const int4*>(st_c)[g4];
+        if (t0 >= 63 && t0 + 3 < m) {
+          // every lane is inside the matrix: no range test; local optima are tracked per 4 steps
+          int32_t hk[4][R];
+          step(t0, vh.x, ve.x, vc.x, std::false_type(), hk[0]);
+          step(t0 + 1, vh.y, ve.y, vc.y, std::false_type(), hk[1]);
+          step(t0 + 2, vh.z, ve.z, vc.z, std::false_type(), hk[2]);
+          step(t0 + 3, vh.w, ve.w, vc.w, std::false_type(), hk[3]);
+          if (MODE == ALN_LOCAL) {
+            bool imp = false;
+#pragma unroll
+            for (int r = 0; r < R; ++r) imp |= max(max(hk[0][r], hk[1][r]), max(hk[2][r], hk[3][r])) > bv[r];
+            if (imp) {
+#pragma unroll
+              for (int k = 0; k < 4; ++k)
+#pragma unroll
+                for (int r = 0; r < R; ++r)
+                  if (hk[k][r] > bv[r]) {
+                    bv[r] = hk[k][r];
+                    bj[r] = t0 + k - lane + 1;
+                  }
+            }
+          }
+        } else {
+          step(t0, vh.x, ve.x, vc.x, std::true_type(), nullptr);
+          step(t0 + 1, vh.y, ve.y, vc.y, std::true_type(), nullptr);
+          step(t0 + 2, vh.z, ve.z, vc.z, std::true_type(), nullptr);
+          step(t0 + 3, vh.w, ve.w, vc.w, std::true_type(), nullptr);
+        }
+      }
+      // lanes 64-BLK.. hold lane 63's outputs of steps tb..tb+BLK-1, i.e. columns tb-62..tb+BLK-63
+      if (has_out) {
+        const int hi = min(tb + BLK - 63, m);
+        const int col_out = tb + (lane - (64 - BLK)) - 62;
+        const bool mine = lane >= 64 - BLK && col_out >= 1 && col_out <= m;
+        if (hi >= 1) {
+          if (!lds_wait_ge(&con[wib + 1], hi - kRing)) {  // the band below has read what this overwrites
+            failed = true;
+            break;
+          }
+          if (mine) rout[col_out % kRing] = make_int2(out_h, out_e);
+          asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+          if (lane == 0) __hip_atomic_store(&pub[wib + 1], hi, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
+      }
+    }
+
+    // band optimum: (score, i, j) over this lane's rows, then across the wave
+    int bs = kNeg32, bi = 0, bjj = 0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int i = irow0 + r + 1;
+      if (i > n) continue;
+      int sc = 0, jj = 0;
+      bool cand = false;
+      if (MODE == ALN_LOCAL) {
+        sc = bv[r] + i * ge;
+        jj = bj[r];
+        cand = sc > 0;
+      } else if (MODE == ALN_SEMIGLOBAL) {
+        sc = hl[r] + i * ge;  // H(i, m): last-column candidate; row n is handled below
+        jj = m;
+        cand = (i < n);
+      } else {
+        sc = hl[r] + i * ge;
+        jj = m;
+        cand = (i == n);
+      }
+      // a flipped pair's cell (i, jj) is the call's cell (jj, i)
+      const int ci = flip ? jj : i, cj = flip ? i : jj;
+      if (cand && better(sc, ci, cj, bs, bi, bjj)) {
+        bs = sc;
+        bi = ci;
+        bjj = cj;
+      }
+    }
+    if (MODE == ALN_SEMIGLOBAL && last_band && rn >= 0 && rn < R) {
+      // row n: (n, 0) with H = 0 first, then its running maximum over j in column order
+      const int rowv = (browj > 0) ? brow + n * ge : 0;
+      const int ci = flip ? browj : n, cj = flip ? n : browj;
+      if (better(rowv, ci, cj, bs, bi, bjj)) {
+        bs = rowv;
+        bi = ci;
+        bjj = cj;
+      }
+    }
+    for (int o = 32; o >= 1; o >>= 1) {
+      const int s2 = __shfl_xor(bs, o, 64), i2 = __shfl_xor(bi, o, 64), j2 = __shfl_xor(bjj, o, 64);
+      if (better(s2, i2, j2, bs, bi, bjj)) {
+        bs = s2;
+        bi = i2;
+        bjj = j2;
+      }
+    }
+    const bool anybad = __any(bad);
+    if (lane == 0) W.band_res[t] = make_int4(bs, bi, bjj, (anybad ? 1 : 0) | (failed ? 2 : 0));
+    }
+    __syncthreads();  // the group's rings and ticket are reused by the next group
+  }
+}
+
 // One wave per pair: reduces the pair's band optima into its aln_result_t.
 template <int MODE, bool TB>
 __global__ __launch_bounds__(256) void wf_finish_kernel(const KParams P, WfWs W, aln_result_t* __restrict__ out,
@@ -503,42 +953,48 @@ __global__ void wf_single_pair_kernel(WfWs W, int n, int m, int band_rows) {
 }
 
 template <int MODE, bool AFFINE, int PROF, bool TB>
-void launch_wf_t(const KParams& kp, const uint8_t* q, const uint8_t* s, const WfWs& W, int n_waves,
+void launch_wf_t(const KParams& kp, const uint8_t* q, const uint8_t* s, const WfWs& W, int n_waves, bool grouped,
                  hipStream_t stream) {
   const int blocks = (n_waves + kWfWavesPerBlock - 1) / kWfWavesPerBlock;
   const size_t lds = PROF == kProfLane ? (size_t)kWfWavesPerBlock * kp.alphabet * 64 * sizeof(uint32_t) : 0;
   ProfScope prof(TB ? "wavefront_i32_traceback" : "wavefront_i32", stream);
-  hipLaunchKernelGGL((wf_i32_kernel<MODE, AFFINE, PROF, TB, kWfR>), dim3(blocks), dim3(kWfBlock), lds, stream, kp,
-                     q, s, W);
+  if (grouped)
+    hipLaunchKernelGGL((wf_i32_group_kernel<MODE, AFFINE, PROF, TB, kWfR>), dim3(blocks), dim3(kWfBlock), lds,
+                       stream, kp, q, s, W);
+  else
+    hipLaunchKernelGGL((wf_i32_kernel<MODE, AFFINE, PROF, TB, kWfR>), dim3(blocks), dim3(kWfBlockAlone), lds,
+                       stream, kp, q, s, W);
 }
 
 template <int MODE, bool AFFINE, bool TB>
-void launch_wf_p(const KParams& kp, const uint8_t* q, const uint8_t* s, const WfWs& W, int nw, hipStream_t st) {
+void launch_wf_p(const KParams& kp, const uint8_t* q, const uint8_t* s, const WfWs& W, int nw, bool grouped,
+                 hipStream_t st) {
   const bool bytes = kp.sigma_max - kp.ge <= 127 && kp.sigma_min - kp.ge >= -127;
   if (bytes && kp.alphabet <= 4)
-    launch_wf_t<MODE, AFFINE, kProfReg, TB>(kp, q, s, W, nw, st);
+    launch_wf_t<MODE, AFFINE, kProfReg, TB>(kp, q, s, W, nw, grouped, st);
   else if (bytes)
-    launch_wf_t<MODE, AFFINE, kProfLane, TB>(kp, q, s, W, nw, st);
+    launch_wf_t<MODE, AFFINE, kProfLane, TB>(kp, q, s, W, nw, grouped, st);
   else
-    launch_wf_t<MODE, AFFINE, kProfTable, TB>(kp, q, s, W, nw, st);
+    launch_wf_t<MODE, AFFINE, kProfTable, TB>(kp, q, s, W, nw, grouped, st);
 }
 
 template <int MODE, bool TB>
-void launch_wf_m(const KParams& kp, const uint8_t* q, const uint8_t* s, const WfWs& W, int nw, hipStream_t st) {
+void launch_wf_m(const KParams& kp, const uint8_t* q, const uint8_t* s, const WfWs& W, int nw, bool grouped,
+                 hipStream_t st) {
   if (kp.go != 0)
-    launch_wf_p<MODE, true, TB>(kp, q, s, W, nw, st);
+    launch_wf_p<MODE, true, TB>(kp, q, s, W, nw, grouped, st);
   else
-    launch_wf_p<MODE, false, TB>(kp, q, s, W, nw, st);
+    launch_wf_p<MODE, false, TB>(kp, q, s, W, nw, grouped, st);
 }
 
 template <int MODE>
-void launch_wf_mode(const KParams& kp, const uint8_t* q, const uint8_t* s, const WfWs& W, int nw, bool tb,
+void launch_wf_mode(const KParams& kp, const uint8_t* q, const uint8_t* s, const WfWs& W, int nw, bool grouped, bool tb,
                     aln_result_t* out, uint32_t* cigar, int64_t cap, hipStream_t st) {
   if (tb) {
-    launch_wf_m<MODE, true>(kp, q, s, W, nw, st);
+    launch_wf_m<MODE, true>(kp, q, s, W, nw, grouped, st);
     hipLaunchKernelGGL((wf_finish_kernel<MODE, true>), dim3(256), dim3(256), 0, st, kp, W, out, cigar, cap);
   } else {
-    launch_wf_m<MODE, false>(kp, q, s, W, nw, st);
+    launch_wf_m<MODE, false>(kp, q, s, W, nw, grouped, st);
     hipLaunchKernelGGL((wf_finish_kernel<MODE, false>), dim3(256), dim3(256), 0, st, kp, W, out, cigar, cap);
   }
 }
@@ -589,18 +1045,18 @@ WfWs wf_view(void* base_, const WfOffsets& o) {
 }
 
 aln_status_t launch_wf_i32(const KParams& kp, const WfWs& W, const uint8_t* q, const uint8_t* s,
-                           aln_result_t* out, int max_waves, bool tb, uint32_t* cigar, int64_t cigar_cap,
-                           hipStream_t stream) {
+                           aln_result_t* out, int max_waves, bool grouped, bool tb, uint32_t* cigar,
+                           int64_t cigar_cap, hipStream_t stream) {
   hipLaunchKernelGGL(wf_reset_kernel, dim3(256), dim3(256), 0, stream, W);
   switch (kp.mode) {
     case ALN_GLOBAL:
-      launch_wf_mode<ALN_GLOBAL>(kp, q, s, W, max_waves, tb, out, cigar, cigar_cap, stream);
+      launch_wf_mode<ALN_GLOBAL>(kp, q, s, W, max_waves, grouped, tb, out, cigar, cigar_cap, stream);
       break;
     case ALN_LOCAL:
-      launch_wf_mode<ALN_LOCAL>(kp, q, s, W, max_waves, tb, out, cigar, cigar_cap, stream);
+      launch_wf_mode<ALN_LOCAL>(kp, q, s, W, max_waves, grouped, tb, out, cigar, cigar_cap, stream);
       break;
     default:
-      launch_wf_mode<ALN_SEMIGLOBAL>(kp, q, s, W, max_waves, tb, out, cigar, cigar_cap, stream);
+      launch_wf_mode<ALN_SEMIGLOBAL>(kp, q, s, W, max_waves, grouped, tb, out, cigar, cigar_cap, stream);
       break;
   }
   return hipGetLastError() == hipSuccess ? ALN_OK : ALN_E_DEVICE;
@@ -629,7 +1085,9 @@ aln_status_t launch_long(const KParams& kp, const LongPlan& pl, const uint8_t* q
                          hipStream_t stream) {
   WfWs W = wf_view(ws, pl.off);
   hipLaunchKernelGGL(wf_single_pair_kernel, dim3(1), dim3(64), 0, stream, W, (int)n, (int)m, kWfBand);
-  return launch_wf_i32(kp, W, q, s, out, pl.n_waves, pl.tb, cigar, cigar_cap, stream);
+  // one pair: its bands are few per SIMD, so the grouped engine (no device-memory stalls in the
+  // compute waves) is the faster one
+  return launch_wf_i32(kp, W, q, s, out, pl.n_waves, true, pl.tb, cigar, cigar_cap, stream);
 }
 
 }  // namespace mialign

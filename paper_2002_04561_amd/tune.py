@@ -28,10 +28,11 @@ from . import AlnError, BatchConfig
 SEARCH = (
     ("wf_min_cells", (1, 1 << 12, 1 << 14, 1 << 16, 1 << 18, 1 << 20, -1)),
     ("wf_waves_per_cu", (8, 12, 16, 20, 24, 32, 4)),
+    ("wf_group", (1, 4)),
     ("wf_orient", (2, 1, -1)),
     ("small_bits", (16, 32)),
 )
-START = dict(wf_min_cells=1 << 16, wf_waves_per_cu=16, wf_orient=-1, small_bits=16)
+START = dict(wf_min_cells=1 << 16, wf_waves_per_cu=16, wf_orient=-1, small_bits=16, wf_group=0)
 # One lane runs a pair's whole matrix in the one-pair-per-lane kernels: thresholds that would leave
 # pairs above this many cells there are not tried (a single such pair takes tens of milliseconds).
 LANE_CELLS_MAX = 1 << 22

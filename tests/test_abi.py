@@ -64,6 +64,10 @@ def test_batch_config_validation_on_host():
         st = aln.lib().aln_align_batch_ex(ctypes.byref(sc), 0, None, None, None, None, 0, 0, 0, 0, 0, ctypes.byref(c),
                                           None, None, None, None, 0, None)
         assert st == e, (cfg, st)
+    c = aln.BatchConfig(wf_group=2).c()
+    st = aln.lib().aln_align_batch_ex(ctypes.byref(sc), 0, None, None, None, None, 0, 0, 0, 0, 0, ctypes.byref(c),
+                                      None, None, None, None, 0, None)
+    assert st == -1
     c = aln.BatchConfig().c()
     c.reserved[1] = 5
     st = aln.lib().aln_align_batch_ex(ctypes.byref(sc), 0, None, None, None, None, 0, 0, 0, 0, 0, ctypes.byref(c),

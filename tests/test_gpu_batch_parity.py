@@ -174,7 +174,8 @@ WF_SCHEMES = {
 @pytest.mark.parametrize("mode", [0, 1, 2], ids=["global", "local", "semi"])
 @pytest.mark.parametrize("scheme", list(WF_SCHEMES))
 @pytest.mark.parametrize("orient", [1, -1, 2], ids=["oriented", "as_given", "cheaper"])
-def test_wavefront_every_pair(gpu, mode, scheme, orient):
+@pytest.mark.parametrize("group", [1, 4], ids=["alone", "grouped"])
+def test_wavefront_every_pair(gpu, mode, scheme, orient, group):
     """Every non-empty pair on the band wavefront (wf_min_cells = 1), lengths log-uniform 1..1500 in both
     directions, so that pairs run transposed (orient = 1, the longer sequence along the rows) or as given;
     results must not depend on it, ties included."""
@@ -189,7 +190,7 @@ def test_wavefront_every_pair(gpu, mode, scheme, orient):
     q, qo = synth.pack(qs)
     s, so = synth.pack(ss)
     w = synth.Workload("wf_" + scheme, mode, A, go, ge, q, qo, s, so, match=ma, mismatch=mi, subst=sub)
-    cfg = aln.BatchConfig(wf_min_cells=1, wf_orient=orient)
+    cfg = aln.BatchConfig(wf_min_cells=1, wf_orient=orient, wf_group=group)
     gres, _ = run_gpu(w, aln.SCORE_ONLY, config=cfg)
     ores, _ = run_oracle(w, False)
     bad = compare(w, gres, None, ores, None, "wf/%s/%d" % (scheme, orient))
@@ -197,11 +198,12 @@ def test_wavefront_every_pair(gpu, mode, scheme, orient):
 
 
 @pytest.mark.parametrize("waves", [1, 4, 16, 32])
-def test_wavefront_waves_per_cu(gpu, waves):
+@pytest.mark.parametrize("group", [1, 4], ids=["alone", "grouped"])
+def test_wavefront_waves_per_cu(gpu, waves, group):
     """The persistent grid size changes nothing: few waves per CU (long queues) and many."""
     import paper_2002_04561_amd as aln
     w = _workload(880 + waves, 120, 100, 2500, 1, "prot_affine")
-    cfg = aln.BatchConfig(wf_min_cells=1 << 14, wf_waves_per_cu=waves)
+    cfg = aln.BatchConfig(wf_min_cells=1 << 14, wf_waves_per_cu=waves, wf_group=group)
     gres, _ = run_gpu(w, aln.SCORE_ONLY, config=cfg)
     ores, _ = run_oracle(w, False)
     bad = compare(w, gres, None, ores, None, "waves %d" % waves)
