@@ -88,12 +88,15 @@ __global__ __launch_bounds__(kI16Block) void batch_i16_kernel(
     tab[k] = v;
   }
   __syncthreads();
-  const int AP = P.alphabet + 1;  // profile letters: the alphabet and the pad
+  const int AP = P.alphabet;  // profile letters per pair; past a subject's end, the shared pad row
   const int lane = threadIdx.x & 63;
   const int wib = threadIdx.x >> 6;
-  short* __restrict__ prof = reinterpret_cast<short*>(smem + kTab * kTab * 4) + (size_t)wib * 128 * AP * R;
-  short* __restrict__ profA = prof + (size_t)lane * AP * R;
-  short* __restrict__ profB = prof + (size_t)(64 + lane) * AP * R;
+  // per wave: the pad row (R scores of kPadSigma16, the same for every pair), then the profiles
+  short* __restrict__ prof = reinterpret_cast<short*>(smem + kTab * kTab * 4) + (size_t)wib * (R + 128 * AP * R);
+  const short* __restrict__ padrow = prof;
+  short* __restrict__ profA = prof + R + (size_t)lane * AP * R;
+  short* __restrict__ profB = prof + R + (size_t)(64 + lane) * AP * R;
+  if (lane < R) prof[lane] = (short)kPadSigma16;  // read only by this wave, after its own writes
 
   const int64_t wave = (int64_t)blockIdx.x * kI16WavesPerBlock + wib;
   char* slab = ws + wave * slab_bytes;
@@ -219,8 +222,8 @@ __global__ __launch_bounds__(kI16Block) void batch_i16_kernel(
         s2 hup = from_bits(top.x), eup = from_bits(top.y);
         s2 hd = hdiag;
         hdiag = hup;
-        const uint32_t* pa = reinterpret_cast<const uint32_t*>(profA + ca * R);
-        const uint32_t* pb = reinterpret_cast<const uint32_t*>(profB + cb * R);
+        const uint32_t* pa = reinterpret_cast<const uint32_t*>(ca < AP ? profA + ca * R : padrow);
+        const uint32_t* pb = reinterpret_cast<const uint32_t*>(cb < AP ? profB + cb * R : padrow);
         uint32_t wa[R / 2], wb[R / 2];
 #pragma unroll
         for (int r = 0; r < R / 2; ++r) {
@@ -403,7 +406,7 @@ __global__ __launch_bounds__(kI16Block) void batch_i16_kernel(
 template <int MODE, bool AFFINE, bool TB, int R>
 void launch_i16_t(const KParams& kp, const BatchPlan16& pl, const I16Args& a, hipStream_t stream) {
   const int blocks = (pl.n_waves + kI16WavesPerBlock - 1) / kI16WavesPerBlock;
-  const size_t lds = (size_t)kTab * kTab * 4 + (size_t)kI16WavesPerBlock * 128 * (kp.alphabet + 1) * R * 2;
+  const size_t lds = (size_t)kTab * kTab * 4 + (size_t)kI16WavesPerBlock * (R + 128 * kp.alphabet * R) * 2;
   ProfScope prof(TB ? "batch_i16_traceback" : "batch_i16_score", stream);
   hipLaunchKernelGGL((batch_i16_kernel<MODE, AFFINE, TB, R>), dim3(blocks), dim3(kI16Block), lds, stream, kp, a.q,
                      a.q_off, a.s, a.s_off, pl.n_pairs, pl.max_n, pl.max_m, a.out, a.cigar, a.cigar_off,
