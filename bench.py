@@ -1,5 +1,5 @@
 #!/usr/bin/env python3
-"""Benchmark of the alignment hot path on one MI355X: GCUPS, bit-exact against the oracle.
+"""Benchmark of the alignment hot path on one MI355X: GCUPS, checked against stored oracle results.
 
   python bench.py [--steps K] [--warmup W] [--workload NAME] [--no-cpu-baseline]
 
@@ -9,6 +9,7 @@ traceback when the workload asks for CIGARs).  Prints one JSON line.
 
 Workloads (synth/__init__.py has the recipes):
   long     1 pair 262144 x 262144 DNA, local affine (-3/-1, +2/-3), score + end cell       [default]
+  long_tb  the same pair with its CIGAR (4-bit predecessor codes of all cells held in HBM, ~34 GB)
   reads    1,048,576 read/window pairs, semi-global affine (-5/-2, +1/-4), CIGAR for every pair
   protein  65,536 protein pairs, lengths log-uniform 64..16384, local affine (-11/-1), score-only
   nw1k     1 pair 1000 x 1000 DNA, global linear (+2/-1, gap -1), CIGAR
@@ -43,6 +44,9 @@ def make_workload(name, pairs=None):
     import synth
     if name == "long":
         return synth.long_dna_local()
+    if name == "long_tb":
+        import dataclasses
+        return dataclasses.replace(synth.long_dna_local(), traceback=True)
     if name == "reads":
         return synth.reads_semiglobal(n_pairs=pairs or (1 << 20))
     if name == "protein":
@@ -115,37 +119,44 @@ def run_cpu_baseline(w, budget_s=15.0):
                 k2, w.n_pairs, float(csum[k2 - 1]), "with traceback" if w.traceback else "score-only", dt)}
 
 
-def sample_indices(w, count=64, seed=0):
-    rng = np.random.default_rng(seed)
-    return rng.choice(w.n_pairs, size=min(count, w.n_pairs), replace=False)
+GOLDEN = {"long_dna_local_262144": "long_local_262144.json", "long_dna_global_1k": "global_1k.json",
+          "reads_semiglobal": "reads_sample.json", "protein_uneven": "protein_sample.json"}
 
 
-def spot_check(w, res, cigars, idx):
-    """Compares sampled pairs bit-exactly with the oracle (one by one)."""
-    import oracle
-    sc = _oracle_scoring(w)
-    for k in idx:
-        a, b = w.pair(int(k))
-        if w.n_pairs == 1 and len(a) * len(b) > 4e8:
-            g = os.path.join(ROOT, "tests", "golden", "long_local_262144.json")
-            if w.name == "long_dna_local_262144" and os.path.exists(g):
-                gold = json.load(open(g))
-                ok = (int(res["score"][0]), int(res["q_end"][0]), int(res["s_end"][0])) == \
-                     (gold["score"], gold["q_end"], gold["s_end"])
-                return ("bit-exact vs the stored oracle value" if ok else "MISMATCH vs the stored oracle value")
-            return "not checked (pair too large for a one-by-one oracle run)"
-        if w.traceback:
-            r = oracle.align(sc, a, b, traceback=True)
-            g = (int(res["score"][k]), int(res["q_begin"][k]), int(res["q_end"][k]), int(res["s_begin"][k]),
-                 int(res["s_end"][k]), cigars[k])
-            o = (r.score, r.q_begin, r.q_end, r.s_begin, r.s_end, r.cigar)
-        else:
-            r = oracle.align(sc, a, b, impl="linspace")
-            g = (int(res["score"][k]), int(res["q_end"][k]), int(res["s_end"][k]))
-            o = (r.score, r.q_end, r.s_end)
+def _cigar_string(runs):
+    return "".join("%d%s" % (n, "MID"[op]) for n, op in runs)
+
+
+def golden_pairs(w):
+    """Indices of the pairs whose expected results tests/golden/ holds for this workload (written there by
+    tests/golden/make_golden.py from the oracle), or None."""
+    path = os.path.join(ROOT, "tests", "golden", GOLDEN.get(w.name, "-"))
+    if not os.path.exists(path):
+        return None, None
+    g = json.load(open(path))
+    if "pairs" in g:
+        if g["n_pairs"] != w.n_pairs or bool(g["traceback"]) != bool(w.traceback):
+            return None, None
+        return [p["k"] for p in g["pairs"]], g["pairs"]
+    return [0], [dict(g, k=0)]
+
+
+def spot_check(w, res, cigars, idx, expect):
+    """Compares pairs bit-exactly with the oracle's stored results (score, end cell, and the begin cell and
+    CIGAR when traced back)."""
+    if expect is None:
+        return "not checked (no stored oracle values for this workload)"
+    for e in expect:
+        k = int(e["k"])
+        g = (int(res["score"][k]), int(res["q_end"][k]), int(res["s_end"][k]))
+        o = (e["score"], e["q_end"], e["s_end"])
         if g != o:
             return "MISMATCH pair %d" % k
-    return "bit-exact on %d sampled pairs" % len(idx)
+        if w.traceback and "cigar" in e:
+            g = (int(res["q_begin"][k]), int(res["s_begin"][k]), _cigar_string(cigars[k]))
+            if g != (e["q_begin"], e["s_begin"], e["cigar"]):
+                return "MISMATCH pair %d (CIGAR)" % k
+    return "bit-exact vs the stored oracle values of %d pair(s)" % len(expect)
 
 
 def time_graph(ba, stream, steps):
@@ -286,7 +297,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="long", choices=["long", "reads", "protein", "nw1k", "serve"])
+    ap.add_argument("--workload", default="long", choices=["long", "long_tb", "reads", "protein", "nw1k", "serve"])
     ap.add_argument("--requests", type=int, default=1000, help="serve: number of requests")
     ap.add_argument("--rate", type=float, default=15.0, help="serve: Poisson arrival rate (requests/s)")
     ap.add_argument("--budget-gb", type=int, default=64, help="serve: device memory budget (GiB)")
@@ -372,12 +383,13 @@ def main():
     log("%.3f ms/step, %.1f GCUPS; kernels %s" % (ms, gcups, prof))
 
     res = ba.result().reshape(1) if long_path else ba.results()
-    idx = sample_indices(w)
+    idx, expect = golden_pairs(w)
+    idx = idx or []
     if long_path:
         cigars = {0: ba.cigar_runs()} if w.traceback else None
     else:
         cigars = ba.cigars(idx) if w.traceback else None
-    check = "skipped" if args.no_check else spot_check(w, res, cigars, idx)
+    check = "skipped" if args.no_check else spot_check(w, res, cigars, idx, expect)
     log("parity:", check)
 
     gap = "linear" if w.gap_open == 0 else "affine"

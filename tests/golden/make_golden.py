@@ -42,7 +42,36 @@ def global_1k():
             "s_end": r.s_end, "cigar": oracle.cigar_string(r.cigar)}
 
 
-JOBS = {"long_local_262144": long_local_262144, "global_1k": global_1k}
+def _sample(w, traceback, count=64, seed=0):
+    """The oracle's results on a seeded sample of a batch's pairs (the pairs bench.py checks)."""
+    import numpy as np
+    idx = np.random.default_rng(seed).choice(w.n_pairs, size=min(count, w.n_pairs), replace=False)
+    sc = _sc(w)
+    out = []
+    for k in idx:
+        a, b = w.pair(int(k))
+        if traceback:
+            r = oracle.align(sc, a, b, traceback=True)
+            out.append({"k": int(k), "score": r.score, "q_begin": r.q_begin, "q_end": r.q_end, "s_begin": r.s_begin,
+                        "s_end": r.s_end, "cigar": oracle.cigar_string(r.cigar)})
+        else:
+            r = oracle.align(sc, a, b, impl="linspace")
+            out.append({"k": int(k), "score": r.score, "q_end": r.q_end, "s_end": r.s_end})
+    return {"workload": w.name, "n_pairs": w.n_pairs, "traceback": traceback, "pairs": out}
+
+
+def reads_sample():
+    """64 seeded pairs of the 2^20 read/window batch (semi-global affine) with their canonical CIGARs."""
+    return _sample(synth.reads_semiglobal(n_pairs=1 << 20), True)
+
+
+def protein_sample():
+    """64 seeded pairs of the 65536-pair protein batch (local affine), score and end cell."""
+    return _sample(synth.protein_uneven(n_pairs=65536), False)
+
+
+JOBS = {"long_local_262144": long_local_262144, "global_1k": global_1k, "reads_sample": reads_sample,
+        "protein_sample": protein_sample}
 
 if __name__ == "__main__":
     names = sys.argv[1:] or list(JOBS)

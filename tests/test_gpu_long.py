@@ -157,3 +157,22 @@ def test_long_traceback_truncation(gpu):
     full = _run_tb(q, s, 0, 4, -3, -1, 2, -3)
     short = _run_tb(q, s, 0, 4, -3, -1, 2, -3, cap=2)
     assert full[7] > 2 and short[6] & 2 and short[7] == full[7]
+
+
+@pytest.mark.slow
+def test_long_traceback_full_262144(gpu):
+    """Traceback of the full 262144 x 262144 local affine pair, with the 4-bit predecessor code of every cell held
+    in HBM (about 34 GB): score and end cell equal the stored oracle value, and the CIGAR re-scores to exactly that
+    score over q[q_begin:q_end] x s[s_begin:s_end]."""
+    from helpers import rescore
+    path = os.path.join(HERE, "golden", "long_local_262144.json")
+    if not os.path.exists(path):
+        pytest.skip("golden value not generated")
+    g = json.load(open(path))
+    w = synth.long_dna_local(seed=2, n=262144)
+    a, b = w.pair(0)
+    score, qb, qe, sb, se, runs, flags, clen = _run_tb(a, b, 1, 4, -3, -1, 2, -3)
+    assert flags == 0 and (score, qe, se) == (g["score"], g["q_end"], g["s_end"])
+    assert clen == len(runs) > 0 and 0 <= qb < qe and 0 <= sb < se
+    total, i, j = rescore(1, w.sigma_table(), -3, -1, a, b, qb, sb, runs)
+    assert (total, i, j) == (score, qe, se)
