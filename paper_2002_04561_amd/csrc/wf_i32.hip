@@ -836,9 +836,13 @@ __global__ __launch_bounds__(kWfBlock) void wf_i32_group_kernel(const KParams P,
 }
 
 // One wave per pair: reduces the pair's band optima into its aln_result_t.
+constexpr int kWalkGroups = 16;  // row groups (of kWfR rows) in a traceback window
+constexpr int kWalkCols = 64;    // columns in a traceback window
+
 template <int MODE, bool TB>
 __global__ __launch_bounds__(256) void wf_finish_kernel(const KParams P, WfWs W, aln_result_t* __restrict__ out,
                                                         uint32_t* __restrict__ cigar, int64_t cigar_cap) {
+  __shared__ uint16_t walk_win[TB ? 4 : 1][TB ? kWalkGroups * kWalkCols : 1];
   const int lane = threadIdx.x & 63;
   const int np = *W.n_pairs;
   const bool err = __hip_atomic_load(W.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
@@ -863,7 +867,7 @@ __global__ __launch_bounds__(256) void wf_finish_kernel(const KParams P, WfWs W,
         bj = j2;
       }
     }
-    if (lane != 0) continue;
+    // every lane now holds the same optimum; the result is computed by all and written by lane 0
     const int n = pr.flip ? pr.m : pr.n, m = pr.flip ? pr.n : pr.m;  // the call's query and subject lengths
     aln_result_t r;
     r.q_begin = -1;
@@ -897,11 +901,26 @@ __global__ __launch_bounds__(256) void wf_finish_kernel(const KParams P, WfWs W,
       r.s_end = 0;
     }
     if (TB && r.flags == 0) {
+      // The codes form a [row group][column] array of 16-bit words, 4 rows per word (band bb, lane L
+      // is row group bb * 64 + L).  The whole wave walks in lockstep: a window of kWalkGroups row
+      // groups x kWalkCols columns ending at the current cell is loaded into LDS by all lanes, and
+      // the walk reads it there until it steps out of the window.
       const uint16_t* __restrict__ codes = W.codes + pr.code_off;
+      uint16_t* __restrict__ win = walk_win[threadIdx.x >> 6];
+      int g0 = -1, c0 = -1;  // the window holds row groups g0-kWalkGroups+1..g0, columns c0-kWalkCols+1..c0
       auto code = [&](int ii, int jj) -> uint32_t {
-        const int bb = (ii - 1) / kWfBand, rr = (ii - 1) % kWfBand;
-        const uint32_t w = codes[((size_t)bb * 64 + (size_t)(rr / kWfR)) * (size_t)m + (size_t)(jj - 1)];
-        return (w >> (4 * (rr % kWfR))) & 15u;
+        const int g = (ii - 1) / kWfR;
+        if (g > g0 || g <= g0 - kWalkGroups || jj > c0 || jj <= c0 - kWalkCols) {
+          g0 = g;
+          c0 = jj;
+          for (int k = lane; k < kWalkGroups * kWalkCols; k += 64) {
+            const int gg = g0 - k / kWalkCols, cc = c0 - k % kWalkCols;
+            win[k] = (gg >= 0 && cc >= 1) ? codes[(size_t)gg * (size_t)m + (size_t)(cc - 1)] : (uint16_t)0;
+          }
+          asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)" ::: "memory");  // the window is in LDS before it is read
+        }
+        const uint32_t w = win[(g0 - g) * kWalkCols + (c0 - jj)];
+        return (w >> (4 * ((ii - 1) % kWfR))) & 15u;
       };
       int qbeg, sbeg, runs;
       walk_back<MODE>(code, r.q_end, r.s_end, cigar, cigar_cap, &qbeg, &sbeg, &runs);
@@ -910,7 +929,7 @@ __global__ __launch_bounds__(256) void wf_finish_kernel(const KParams P, WfWs W,
       r.cigar_len = runs;
       if (runs > cigar_cap) r.flags |= ALN_RES_CIGAR_TRUNC;
     }
-    out[pr.out_idx] = r;
+    if (lane == 0) out[pr.out_idx] = r;
   }
 }
 
