@@ -24,6 +24,8 @@
 #include "internal.h"
 #include "walk.h"
 
+extern "C" __device__ __attribute__((const)) int __ockl_wfred_max_i32(int);  // maximum over the wave
+
 namespace mialign {
 namespace {
 
@@ -53,6 +55,40 @@ __device__ __forceinline__ int dpp_shr1(int old, int src) {
 }
 __device__ __forceinline__ int dpp_shl1(int old, int src) {
   return __builtin_amdgcn_update_dpp(old, src, 0x130, 0xf, 0xf, false);  // wave_shl:1, lane 63 keeps old
+}
+
+// Local alignment: every row keeps the best biased score it has seen (bv) and the first column that
+// reached it.  The pair's optimum -- the first cell in (score, i, j) order -- scores at least as high
+// as every real cell, so once per block each row's running value is raised to the largest score seen
+// so far minus one (ties still pass, also for transposed pairs, whose caller rows run along the band):
+// the best of the band's top-row inputs, which are cells of an earlier row, and the best its own rows
+// have recorded.  Rows then record only cells that may still be the optimum.  On related sequences
+// the top row stays ahead of the values that climb towards the diagonal inside the band; on unrelated
+// ones the band's best over all its rows is rarely beaten; either way the exact per-cell update runs
+// in a small fraction of the 4-step groups.  A raised value never wins: it is below a real cell,
+// which some band records or beats.  top_h is the top-row Hb (row i0's bias) of the block's columns,
+// or 0 (at most H = 0) on lanes without one.  Rows past n need no mask: with gap scores <= 0 their
+// values come from row n's minus penalties, or from the floor H = 0, so they never exceed the
+// optimum either.  Every lane of the wave calls this.
+template <int R>
+__device__ __forceinline__ void raise_local_floors(int32_t (&bv)[R], const int32_t (&nu)[R], int32_t top_h, int i0,
+                                                   int32_t ge) {
+  static_assert(R % 2 == 0, "rows are folded in pairs");
+  int32_t v = top_h + i0 * ge;  // H of the top-row cell
+#pragma unroll
+  for (int r = 0; r < R; r += 2) v = max(max(v, bv[r] - nu[r]), bv[r + 1] - nu[r + 1]);
+  const int32_t fl = __ockl_wfred_max_i32(v) - 1;
+#pragma unroll
+  for (int r = 0; r < R; ++r) bv[r] = max(bv[r], fl + nu[r]);
+}
+
+// c ? a : b as one v_cndmask on the lane mask of c, so the compiler cannot turn the choice into a
+// branch around the computation of a
+__device__ __forceinline__ int lane_select(bool c, int a, int b) {
+  const unsigned long long mask = __builtin_amdgcn_ballot_w64(c);
+  int r;
+  asm("v_cndmask_b32_e64 %0, %1, %2, %3" : "=v"(r) : "v"(b), "v"(a), "s"(mask));
+  return r;
 }
 
 // (score, i, j) order of optima: larger score, then smaller i, then smaller j.
@@ -228,6 +264,7 @@ __global__ __launch_bounds__(kWfBlockAlone) void wf_i32_kernel(const KParams P, 
           te = (int32_t)(pv >> 32);
         }
       }
+      if (MODE == ALN_LOCAL) raise_local_floors<R>(bv, nu, th, i0, ge);
       st_h[lane] = th;
       st_e[lane] = te;
       st_c[lane] = sreg;
@@ -303,18 +340,24 @@ __global__ __launch_bounds__(kWfBlockAlone) void wf_i32_kernel(const KParams P, 
           step(t0 + 2, vh.z, ve.z, vc.z, std::false_type(), hk[2]);
           step(t0 + 3, vh.w, ve.w, vc.w, std::false_type(), hk[3]);
           if (MODE == ALN_LOCAL) {
+            int32_t mk[R];
             bool imp = false;
 #pragma unroll
-            for (int r = 0; r < R; ++r) imp |= max(max(hk[0][r], hk[1][r]), max(hk[2][r], hk[3][r])) > bv[r];
+            for (int r = 0; r < R; ++r) {
+              mk[r] = max(max(hk[0][r], hk[1][r]), max(hk[2][r], hk[3][r]));
+              imp |= mk[r] > bv[r];
+            }
             if (imp) {
+              // a row that beat its best takes the group's maximum at the first of the 4 steps that
+              // reached it, as a cell-by-cell strict update would
 #pragma unroll
-              for (int k = 0; k < 4; ++k)
-#pragma unroll
-                for (int r = 0; r < R; ++r)
-                  if (hk[k][r] > bv[r]) {
-                    bv[r] = hk[k][r];
-                    bj[r] = t0 + k - lane + 1;
-                  }
+              for (int r = 0; r < R; ++r) {
+                int k = hk[2][r] == mk[r] ? 2 : 3;
+                k = hk[1][r] == mk[r] ? 1 : k;
+                k = hk[0][r] == mk[r] ? 0 : k;
+                bj[r] = lane_select(mk[r] > bv[r], t0 - lane + 1 + k, bj[r]);
+                bv[r] = max(bv[r], mk[r]);
+              }
             }
           }
         } else {
@@ -666,6 +709,7 @@ __global__ __launch_bounds__(kWfBlock) void wf_i32_group_kernel(const KParams P,
         asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
         if (lane == 0) __hip_atomic_store(&con[wib], need, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
       }
+      if (MODE == ALN_LOCAL) raise_local_floors<R>(bv, nu, th, i0, ge);
       if (lane < BLK) {
         st_h[lane] = th;
         st_e[lane] = te;
@@ -743,18 +787,24 @@ __global__ __launch_bounds__(kWfBlock) void wf_i32_group_kernel(const KParams P,
           step(t0 + 2, vh.z, ve.z, vc.z, std::false_type(), hk[2]);
           step(t0 + 3, vh.w, ve.w, vc.w, std::false_type(), hk[3]);
           if (MODE == ALN_LOCAL) {
+            int32_t mk[R];
             bool imp = false;
 #pragma unroll
-            for (int r = 0; r < R; ++r) imp |= max(max(hk[0][r], hk[1][r]), max(hk[2][r], hk[3][r])) > bv[r];
+            for (int r = 0; r < R; ++r) {
+              mk[r] = max(max(hk[0][r], hk[1][r]), max(hk[2][r], hk[3][r]));
+              imp |= mk[r] > bv[r];
+            }
             if (imp) {
+              // a row that beat its best takes the group's maximum at the first of the 4 steps that
+              // reached it, as a cell-by-cell strict update would
 #pragma unroll
-              for (int k = 0; k < 4; ++k)
-#pragma unroll
-                for (int r = 0; r < R; ++r)
-                  if (hk[k][r] > bv[r]) {
-                    bv[r] = hk[k][r];
-                    bj[r] = t0 + k - lane + 1;
-                  }
+              for (int r = 0; r < R; ++r) {
+                int k = hk[2][r] == mk[r] ? 2 : 3;
+                k = hk[1][r] == mk[r] ? 1 : k;
+                k = hk[0][r] == mk[r] ? 0 : k;
+                bj[r] = lane_select(mk[r] > bv[r], t0 - lane + 1 + k, bj[r]);
+                bv[r] = max(bv[r], mk[r]);
+              }
             }
           }
         } else {

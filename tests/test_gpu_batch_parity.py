@@ -197,6 +197,40 @@ def test_wavefront_every_pair(gpu, mode, scheme, orient, group):
     assert not bad, "\n".join(bad[:10])
 
 
+@pytest.mark.parametrize("go", [0, -3], ids=["linear", "affine"])
+@pytest.mark.parametrize("orient", [1, -1], ids=["oriented", "as_given"])
+@pytest.mark.parametrize("group", [1, 4], ids=["alone", "grouped"])
+@pytest.mark.parametrize("tb", [False, True], ids=["score", "traceback"])
+def test_wavefront_local_ties_across_bands(gpu, go, orient, group, tb):
+    """Local optima that tie across band boundaries (bands of 256 rows).  Runs of one letter score
+    H(i, j) = 2 min(i, j), so a whole column or row of cells reaches the optimum; periodic sequences tie
+    on every third diagonal; a shared prefix puts the optimum on or just below a band's last row.  A band
+    only records cells that reach the largest score the band above hands down, so these pin that the
+    first optimum in (score, i, j) order still comes back, transposed or not."""
+    import paper_2002_04561_amd as aln
+    rng = np.random.default_rng(4100 + 10 * group + (orient > 0) + (go != 0) * 2 + tb * 4)
+    run = lambda k: np.zeros(k, dtype=np.uint8)
+    per = lambda k: np.resize(np.array([0, 1, 2], dtype=np.uint8), k)
+    rnd = lambda k: rng.integers(0, 4, k, dtype=np.uint8)
+    pairs = [(run(700), run(300)), (run(300), run(700)), (run(600), run(600)), (run(257), run(1000)),
+             (run(1000), run(257)), (run(256), run(256)), (run(513), run(200)), (run(200), run(513)),
+             (per(750), per(390)), (per(390), per(750)), (per(1024), per(1024))]
+    for cut in (255, 256, 257, 512):
+        x = rnd(cut)
+        pairs.append((np.concatenate([x, rnd(300)]), x.copy()))
+        pairs.append((x.copy(), np.concatenate([x, rnd(300)])))
+        pairs.append((np.concatenate([rnd(40), x, rnd(200)]), np.concatenate([x, x])))
+    q, qo = synth.pack([a for a, _ in pairs])
+    s, so = synth.pack([b for _, b in pairs])
+    w = synth.Workload("ties_bands", 1, 4, go, -1, q, qo, s, so, match=2, mismatch=-3)
+    flags = aln.TRACEBACK if tb else aln.SCORE_ONLY
+    cfg = aln.BatchConfig(wf_min_cells=1, wf_orient=orient, wf_group=group)
+    gres, gcig = run_gpu(w, flags, config=cfg)
+    ores, ocig = run_oracle(w, tb)
+    bad = compare(w, gres, gcig if tb else None, ores, ocig if tb else None, "ties/%d/%d" % (orient, group))
+    assert not bad, "\n".join(bad[:10])
+
+
 @pytest.mark.parametrize("waves", [1, 4, 16, 32])
 @pytest.mark.parametrize("group", [1, 4], ids=["alone", "grouped"])
 def test_wavefront_waves_per_cu(gpu, waves, group):
