@@ -668,29 +668,32 @@ __global__ __launch_bounds__(kWfBlock) void wf_i32_group_kernel(const KParams P,
     int2* __restrict__ rin = ring[wib];       // rows of the band above (b > 0)
     int2* __restrict__ rout = ring[wib + 1];  // this band's bottom row, for the band below
     const bool has_out = b + 1 < nb;
-    // subject letter of column col as the profile kind indexes it (0 past the end)
-    auto letter = [&](int col) -> int {
-      int c = 0;
-      if (col <= m) {
-        c = s[col - 1];
-        if (c >= P.alphabet) {
-          bad = true;
-          c = PROF == kProfTable ? kPad : 0;
-        }
-        if (PROF == kProfReg) c *= 8;
-        if (PROF == kProfLane) c *= 64;
-        if (PROF == kProfTable && flip) c *= kTab;
+    // Subject letters are loaded one block ahead and turned into profile indices only when their block
+    // starts, so the load's latency hides behind a block of steps: the raw letter of column col (-1 past
+    // the end), then the index the profile kind uses (0 past the end).
+    auto letter_raw = [&](int col) -> int { return col <= m ? (int)s[col - 1] : -1; };
+    auto letter_idx = [&](int c) -> int {
+      if (c < 0) return 0;
+      if (c >= P.alphabet) {
+        bad = true;
+        c = PROF == kProfTable ? kPad : 0;
       }
+      if (PROF == kProfReg) c *= 8;
+      if (PROF == kProfLane) c *= 64;
+      if (PROF == kProfTable && flip) c *= kTab;
       return c;
     };
-    int c_next = lane < BLK ? letter(1 + lane) : 0;  // prefetched one block ahead
+    int c_next = lane < BLK ? letter_raw(1 + lane) : -1;
 
     const int steps = m + 63;
     for (int tb = 0; tb < steps; tb += BLK) {
       // lane-0 inputs for steps tb..tb+BLK-1 (columns tb+1..tb+BLK), held by lanes < BLK
       const int col_in = tb + 1 + lane;
-      const int sreg = c_next;
-      c_next = lane < BLK ? letter(col_in + BLK) : 0;
+      const int sreg = letter_idx(c_next);
+      // consume the previous block's load before issuing the next one: memory counters drain in order,
+      // so waiting for the old letter must not also wait for the new load
+      asm volatile("" ::"v"(sreg) : "memory");
+      c_next = lane < BLK ? letter_raw(col_in + BLK) : -1;
       int32_t th = 0, te = kNeg32;
       if (b == 0) {
         th = (MODE == ALN_GLOBAL) ? go + col_in * ge : 0;
