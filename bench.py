@@ -346,7 +346,8 @@ def main():
     log("workload %s: %d pairs, %.4g cells, generated in %.1f s" % (w.name, w.n_pairs, cells, time.time() - t0))
     stream = torch.cuda.Stream()
     flags = aln.TRACEBACK if w.traceback else aln.SCORE_ONLY
-    long_path = (w.n_pairs == 1)
+    # a single pair runs through aln_align_long, unless an explicit batch config asks for the batch API
+    long_path = (w.n_pairs == 1) and not args.config
     with torch.cuda.stream(stream):
         q, qo, s, so = aln.to_device(w)
         if long_path:
@@ -395,7 +396,7 @@ def main():
     gap = "linear" if w.gap_open == 0 else "affine"
     opc = OPS_PER_CELL[(MODE_NAME[w.mode], gap)]
     dom = max(((k, v) for k, v in prof.items() if k != "plan"), key=lambda kv: kv[1][1]) if prof else None
-    dtype = "int16" if (dom and "i16" in dom[0]) else "int32"
+    dtype = "int16" if (dom and ("i16" in dom[0] or "p16" in dom[0])) else "int32"
     peak = PEAK_I32_TOPS if dtype == "int32" else PEAK_I16_TOPS
     roof = None
     if dom:

@@ -137,7 +137,8 @@ aln_status_t aln_align_batch(const aln_scoring_t* scoring, int64_t n_pairs, cons
  * zero field selects the default.
  *   wf_min_cells     score-only calls: pairs with n*m >= wf_min_cells run on the band wavefront
  *                    engine, the others one pair per lane.  0 => 2^16; negative => no pair.
- *   wf_waves_per_cu  persistent waves per compute unit of the wavefront engine, 1..32; 0 => 16
+ *   wf_waves_per_cu  persistent waves per compute unit of the wavefront engine, 1..32; 0 => 16,
+ *                    or for grouped bands 4 per estimated 4-band group per compute unit, 4..16
  *                    (waves beyond what a compute unit holds start as others finish).
  *   wf_orient        score-only calls: how a wavefront pair is laid out.  The transposed problem
  *                    has the same optimum, and ties are still resolved in the (i, j) order of the
@@ -151,14 +152,22 @@ aln_status_t aln_align_batch(const aln_scoring_t* scoring, int64_t n_pairs, cons
  *                    4 => workgroups of 4 consecutive bands handing rows over in LDS, with a courier
  *                    wave for the hand-offs to and from other workgroups.  0 => 4 when the batch has
  *                    fewer than 16 bands per compute unit (estimated from total_q + total_s), else 1.
- *                    aln_align_long always uses 4. */
+ *                    aln_align_long always uses 4.
+ *   wf_bits          wavefront engine, grouped bands of score-only local alignments over alphabets
+ *                    of up to 4 letters: 16 => packed 16-bit cells (two half bands per lane, scores
+ *                    relative to per-block offsets) where the scores' step bound keeps them exact
+ *                    (max|sigma| + |gap_open| + 2 |gap_extend| <= 32), else 32-bit lanes; 32 =>
+ *                    32-bit lanes only.  0 => 32.  Results are identical either way; with one wave
+ *                    per SIMD the packed cells' longer dependent latency leaves them slower on
+ *                    MI355X, so aln_align_long uses 32. */
 typedef struct {
   int64_t wf_min_cells;
   int32_t wf_waves_per_cu;
   int32_t wf_orient;
   int32_t small_bits;
   int32_t wf_group;
-  int32_t reserved[2]; /* must be zero */
+  int32_t wf_bits;
+  int32_t reserved; /* must be zero */
 } aln_batch_config_t;
 
 /* aln_align_batch with explicit execution choices; config == NULL is aln_align_batch.  The

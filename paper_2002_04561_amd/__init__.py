@@ -44,7 +44,8 @@ class aln_scoring_t(ctypes.Structure):
 
 class aln_batch_config_t(ctypes.Structure):
     _fields_ = [("wf_min_cells", ctypes.c_int64), ("wf_waves_per_cu", ctypes.c_int32), ("wf_orient", ctypes.c_int32),
-                ("small_bits", ctypes.c_int32), ("wf_group", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
+                ("small_bits", ctypes.c_int32), ("wf_group", ctypes.c_int32), ("wf_bits", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 @dataclass(frozen=True)
@@ -56,10 +57,11 @@ class BatchConfig:
     wf_orient: int = 0
     small_bits: int = 0
     wf_group: int = 0
+    wf_bits: int = 0
 
     def c(self) -> aln_batch_config_t:
         return aln_batch_config_t(self.wf_min_cells, self.wf_waves_per_cu, self.wf_orient, self.small_bits,
-                                  self.wf_group, (ctypes.c_int32 * 2)(0, 0))
+                                  self.wf_group, self.wf_bits, 0)
 
 
 _lib = None

@@ -159,8 +159,8 @@ static bool cfg_valid(const aln_batch_config_t* c) {
   if (c->wf_orient < -1 || c->wf_orient > 2) return false;
   if (c->small_bits != 0 && c->small_bits != 16 && c->small_bits != 32) return false;
   if (c->wf_group != 0 && c->wf_group != 1 && c->wf_group != 4) return false;
-  for (int k = 0; k < 2; ++k)
-    if (c->reserved[k] != 0) return false;
+  if (c->wf_bits != 0 && c->wf_bits != 16 && c->wf_bits != 32) return false;
+  if (c->reserved != 0) return false;
   return true;
 }
 
@@ -206,7 +206,7 @@ aln_status_t aln_align_batch_ex(const aln_scoring_t* scoring, int64_t n_pairs, c
   launch_split(L.sp, n_pairs, q_off, s_off, max_n, max_m, out, split_ws, stream);
   if (!tb) {
     WfWs W = wf_view(split_ws + L.sp.wf_base, L.sp.wf);
-    st = launch_wf_i32(kp, W, q, s, out, L.sp.wf_waves, L.sp.grouped, false, nullptr, 0, stream);
+    st = launch_wf_i32(kp, W, q, s, out, L.sp.wf_waves, L.sp.grouped, false, L.sp.wf_p16, nullptr, 0, stream);
     if (st != ALN_OK) return st;
   }
   const int* list = reinterpret_cast<const int*>(split_ws + L.sp.off_small_idx);

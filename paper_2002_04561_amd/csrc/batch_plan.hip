@@ -239,17 +239,23 @@ BatchCfg resolve_cfg(const aln_batch_config_t* c) {
   r.wf_min_cells = (int64_t)1 << 16;
   r.wf_group = 0;
   r.wf_waves_per_cu = kWfWavesPerCUDefault;
+  r.waves_given = false;
   r.orient = 0;
   r.small16 = true;
+  r.wf_p16 = false;
   if (!c) return r;
   if (c->wf_min_cells < 0) r.wf_min_cells = INT64_MAX;
   if (c->wf_min_cells > 0) r.wf_min_cells = c->wf_min_cells;
-  if (c->wf_waves_per_cu > 0) r.wf_waves_per_cu = c->wf_waves_per_cu;
+  if (c->wf_waves_per_cu > 0) {
+    r.wf_waves_per_cu = c->wf_waves_per_cu;
+    r.waves_given = true;
+  }
   if (c->wf_group > 0) r.wf_group = c->wf_group;
   if (c->wf_orient < 0) r.orient = 0;
   if (c->wf_orient == 1) r.orient = 1;
   if (c->wf_orient == 2) r.orient = 2;
   if (c->small_bits == 32) r.small16 = false;
+  if (c->wf_bits == 16) r.wf_p16 = true;
   return r;
 }
 
@@ -281,6 +287,16 @@ aln_status_t plan_split(int64_t n_pairs, int64_t total_q, int64_t total_s, bool 
   const int cus = device_cu_count();
   const int64_t est_bands = (total_q + total_s) / (2 * kWfBand);
   sp->grouped = cfg.wf_group == 4 || (cfg.wf_group == 0 && est_bands < (int64_t)16 * (cus > 0 ? cus : 1));
+  if (sp->grouped && !cfg.waves_given && cus > 0) {
+    // Workgroups take their groups in the order they start, wherever they sit, so a grid with more
+    // workgroups than groups can stack several working ones on a compute unit while others idle.
+    // By default the grid holds as many workgroups per compute unit as the estimated groups need
+    // (1..4; a workgroup is 4 compute waves).
+    const int64_t groups = (est_bands + kWfGroupBands - 1) / kWfGroupBands;
+    const int64_t per_cu = std::min<int64_t>(std::max<int64_t>((groups + cus - 1) / cus, 1), 4);
+    sp->wf_waves = wf_waves((int)(kWfGroupBands * per_cu));
+  }
+  sp->wf_p16 = cfg.wf_p16;
   return sp->wf_waves > 0 ? ALN_OK : ALN_E_DEVICE;
 }
 

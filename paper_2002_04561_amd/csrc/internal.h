@@ -140,13 +140,16 @@ aln_status_t launch_batch_i16(const KParams& kp, const BatchPlan16& plan, const 
 
 // wf_i32.hip
 constexpr int kWfWavesPerCUDefault = 16;
+constexpr int kWfGroupBands = 4;  // bands (compute waves) of a workgroup of the grouped wavefront engine
 constexpr int kWfWavesPerCUMax = 32;
 int wf_waves(int per_cu);
 size_t wf_layout(int64_t max_pairs, int64_t max_items, int64_t row_words, int64_t code_words, WfOffsets* o);
 WfWs wf_view(void* base, const WfOffsets& o);
 // grouped: workgroups of 4 consecutive bands with LDS hand-offs and a courier wave for HBM
+// p16: grouped score-only local bands over alphabets of up to 4 letters may use packed 16-bit cells
+// where the scoring's step bound keeps them exact
 aln_status_t launch_wf_i32(const KParams& kp, const WfWs& W, const uint8_t* q, const uint8_t* s, aln_result_t* out,
-                           int max_waves, bool grouped, bool tb, uint32_t* cigar, int64_t cigar_cap,
+                           int max_waves, bool grouped, bool tb, bool p16, uint32_t* cigar, int64_t cigar_cap,
                            hipStream_t stream);
 aln_status_t plan_long(int64_t n, int64_t m, bool tb, LongPlan* plan);
 aln_status_t launch_long(const KParams& kp, const LongPlan& plan, const uint8_t* q, int64_t n, const uint8_t* s,
@@ -159,6 +162,7 @@ struct SplitPlan {
   int orient;         // wavefront pair orientation: 1 longer sequence along the rows, 0 as given, 2 cheaper
   int64_t item_cap, row_cap;  // bands and row-slot entries the workspace holds
   bool grouped;               // the wavefront engine runs workgroups of 4 consecutive bands
+  bool wf_p16;                // grouped score-only local bands may use packed 16-bit cells
   WfOffsets wf;
   size_t off_small_idx, off_small_cnt, off_keys, off_hist, wf_base, total_bytes;
   int wf_waves;
@@ -168,8 +172,10 @@ struct BatchCfg {
   int64_t wf_min_cells;
   int wf_group;  // 0: by the batch's size, 1: bands on their own, 4: groups of 4 bands
   int wf_waves_per_cu;
+  bool waves_given;  // wf_waves_per_cu came from the caller
   int orient;  // 1 longer along the rows, 0 as given, 2 the cheaper of the two
   bool small16;
+  bool wf_p16;  // packed 16-bit wavefront bands where exact
 };
 BatchCfg resolve_cfg(const aln_batch_config_t* c);
 aln_status_t plan_split(int64_t n_pairs, int64_t total_q, int64_t total_s, bool route_big, const BatchCfg& cfg,

@@ -33,10 +33,11 @@ namespace {
 // courier wave.  Consecutive bands of a pair hand their rows to each other through LDS rings; the
 // courier streams the group's first input row from HBM and its last output row to HBM, so only the
 // courier ever waits on device memory.
-constexpr int kWfWavesPerBlock = 4;                   // compute waves (bands) per workgroup
+constexpr int kWfWavesPerBlock = kWfGroupBands;       // compute waves (bands) per workgroup
 constexpr int kWfBlock = 64 * (kWfWavesPerBlock + 1);  // plus the courier
 constexpr int kRing = 256;                            // columns held by one LDS ring
 constexpr int kBlkGrouped = 32;                       // steps between lane-0 input refills, grouped
+constexpr int kCourierChunk = 32;                     // columns a courier moves between HBM and LDS at once
 constexpr int kWfBlockAlone = 64 * kWfWavesPerBlock;  // bands on their own: no courier
 constexpr long long kSpinLimit = 1ll << 22;           // polls of device memory before giving up
 constexpr long long kLdsSpinLimit = 1ll << 26;        // polls of LDS before giving up
@@ -90,6 +91,31 @@ __device__ __forceinline__ int lane_select(bool c, int a, int b) {
   asm("v_cndmask_b32_e64 %0, %1, %2, %3" : "=v"(r) : "v"(b), "v"(a), "s"(mask));
   return r;
 }
+
+// Packed 16-bit bands (local alignment, score only, alphabets of up to 4 letters).  A 32-bit lane
+// register holds two 16-bit cells: rows of the band's upper half (HB = 128 rows) in its low half and
+// rows of the lower half in its high half, the lower half running kP16Delay steps behind so that the
+// two are independent within a step -- the two halves are independent submatrices sharing one vector
+// lane, as in the paper's inter-task vectorisation (Sec. IV-C), and each keeps its scores as 16-bit
+// differences from an offset of its own, as the paper does within a block (Sec. IV-C): the offset is
+// the half's top-row score at the first column of each block of steps.
+typedef short s2 __attribute__((ext_vector_type(2)));
+constexpr int kP16Half = 128;   // rows per half band
+constexpr int kP16Delay = 96;   // steps between the upper and the lower half
+constexpr int kDelayRing = 256; // columns of the upper half's bottom row kept for the lower half
+constexpr int kNeg16 = -32768;  // stands for -infinity; sums saturate, so it stays far below real scores
+
+__device__ __forceinline__ s2 as_s2(int x) { return __builtin_bit_cast(s2, x); }
+__device__ __forceinline__ int as_int(s2 x) { return __builtin_bit_cast(int, x); }
+__device__ __forceinline__ int sat16(int x) { return min(max(x, -32768), 32767); }
+__device__ __forceinline__ int pack16(int lo, int hi) { return (int)(((uint32_t)lo & 0xffffu) | ((uint32_t)hi << 16)); }
+__device__ __forceinline__ int lo16(int x) { return (int)(int16_t)(x & 0xffff); }
+__device__ __forceinline__ int hi16(int x) { return x >> 16; }
+__device__ __forceinline__ int padd(int a, int b) { return as_int(__builtin_elementwise_add_sat(as_s2(a), as_s2(b))); }
+__device__ __forceinline__ int psub(int a, int b) { return as_int(__builtin_elementwise_sub_sat(as_s2(a), as_s2(b))); }
+__device__ __forceinline__ int pmax(int a, int b) { return as_int(__builtin_elementwise_max(as_s2(a), as_s2(b))); }
+// a 16-bit relative score back to an absolute 32-bit one (-infinity stays -infinity)
+__device__ __forceinline__ int unrel16(int rel, int base) { return rel == kNeg16 ? kNeg32 : rel + base; }
 
 // (score, i, j) order of optima: larger score, then smaller i, then smaller j.
 __device__ __forceinline__ bool better(int s1, int i1, int j1, int s2, int i2, int j2) {
@@ -442,7 +468,7 @@ __global__ __launch_bounds__(kWfBlockAlone) void wf_i32_kernel(const KParams P, 
 //   Fb(i,j) = max(Fb(i,j-1) + ge, Hb(i,j-1) + go + ge)
 //   Hb(i,j) = max(Hb(i-1,j-1) + sigma - ge, Eb, Fb [, -i*ge for local])
 // which is Eqs. (1), (4), (5) with every term shifted by the same per-row constant.
-template <int MODE, bool AFFINE, int PROF, bool TB, int R>
+template <int MODE, bool AFFINE, int PROF, bool TB, int R, bool P16>
 __global__ __launch_bounds__(kWfBlock) void wf_i32_group_kernel(const KParams P, const uint8_t* __restrict__ Q,
                                                           const uint8_t* __restrict__ S, WfWs W) {
   static_assert(PROF != kProfLane || R == 4, "a lane profile word holds 4 rows");
@@ -457,6 +483,9 @@ __global__ __launch_bounds__(kWfBlock) void wf_i32_group_kernel(const KParams P,
   __shared__ long long s_t0;                 // first item of the group
   __shared__ int s_err;
   extern __shared__ uint32_t lprof[];        // kProfLane: [wave][letter][lane], alphabet letters
+  static_assert(!P16 || (MODE == ALN_LOCAL && PROF == kProfReg && !TB && R == 4), "packed bands: local, score only");
+  // packed bands: the upper half's bottom row (absolute H, E) on its way to the lower half
+  __shared__ int2 dline[P16 ? kWfWavesPerBlock : 1][P16 ? kDelayRing : 1];
   for (int k = threadIdx.x; k < kTab * kTab; k += blockDim.x) {
     const int a = k / kTab, b = k % kTab;
     tab[k] = (a >= P.alphabet || b >= P.alphabet) ? -kBig32 : (int32_t)P.sig[a * kMaxAlphabet + b] - P.ge;
@@ -494,7 +523,7 @@ __global__ __launch_bounds__(kWfBlock) void wf_i32_group_kernel(const KParams P,
   };
 
   // The courier: for the group's first band (if it has a band above, in another group) it streams
-  // that band's bottom row from HBM into ring 0, 64 columns at a time, once the band above has
+  // that band's bottom row from HBM into ring 0, kCourierChunk columns at a time, once the band above has
   // published them; for the group's last band (if its band below is in another group) it copies
   // ring kWfWavesPerBlock to the pair's row slot in HBM and publishes the band's progress counter
   // once those stores have completed.  HBM rows and counters use device-coherent (sc1) accesses.
@@ -527,7 +556,7 @@ __global__ __launch_bounds__(kWfBlock) void wf_i32_group_kernel(const KParams P,
     while ((in_on && in_done < m_in) || (out_on && out_done < m_out)) {
       bool moved = false;
       if (in_on && in_done < m_in) {
-        const int want = min(in_done + 64, m_in);
+        const int want = min(in_done + kCourierChunk, m_in);
         if (seen < want) seen = __hip_atomic_load(W.flags + (tin - 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (seen >= want &&
             __hip_atomic_load(&con[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) >= want - kRing) {
@@ -545,7 +574,7 @@ __global__ __launch_bounds__(kWfBlock) void wf_i32_group_kernel(const KParams P,
         }
       }
       if (out_on && out_done < m_out) {
-        const int want = min(out_done + 64, m_out);
+        const int want = min(out_done + kCourierChunk, m_out);
         if (__hip_atomic_load(&pub[kWfWavesPerBlock], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) >= want) {
           const int col = out_done + 1 + lane;
           if (col <= want) {
@@ -578,6 +607,293 @@ __global__ __launch_bounds__(kWfBlock) void wf_i32_group_kernel(const KParams P,
     }
   };
 
+
+  // Packed 16-bit band t (see kP16Half): lane l holds rows i0 + 2l + 1, i0 + 2l + 2 of the upper half
+  // in the low 16 bits and the same rows plus kP16Half in the high 16 bits.  The upper half works on
+  // column j = t - l + 1 at step t, the lower half on j - kP16Delay.  Values are the row-biased Hb of
+  // the 32-bit kernel minus the half's offset; each block re-bases both halves on their top-row
+  // scores at the block's first column, so every value of a block stays within a few thousand of its
+  // offset (adjacent cells differ by at most max|sigma| + |go| + 2|ge|, which the host bounds).  The
+  // band's inputs and outputs are absolute 32-bit rows, as for the 32-bit bands.
+  auto p16_band = [&](auto t_) {
+    const int64_t t = t_;
+    const WfPair pr = W.pairs[np == 1 ? 0 : W.item_pair[t]];
+    const int b = (int)(t - pr.item0);
+    const int n = pr.n, m = pr.m, nb = pr.nb;
+    const bool flip = pr.flip != 0;
+    const uint8_t* __restrict__ q = (flip ? S : Q) + pr.q_off;
+    const uint8_t* __restrict__ s = (flip ? Q : S) + pr.s_off;
+    auto sig_rc = [&](int cr, int cc) -> int { return flip ? tab[cc * kTab + cr] : tab[cr * kTab + cc]; };
+    constexpr int HB = kP16Half, D = kP16Delay, BH = 64 * R;
+    const int i0 = b * BH;
+    // half h (0 upper, 1 lower), row r (0, 1): i = i0 + h * HB + 2 lane + r + 1
+    int prof[2][2];
+    int32_t nuA[2][2], bvA[2][2];
+    int bjA[2][2];
+    bool bad = false;
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int r = 0; r < 2; ++r) {
+        const int i = i0 + h * HB + 2 * lane + r + 1;
+        int c = kPad;
+        if (i <= n) {
+          c = q[i - 1];
+          if (c >= P.alphabet) {
+            bad = true;
+            c = kPad;
+          }
+        }
+        uint32_t w = 0;
+        for (int a = 0; a < 4; ++a) {
+          const int v = (c < P.alphabet && a < P.alphabet) ? sig_rc(c, a) : -128;
+          w |= ((uint32_t)(v & 0xff)) << (8 * a);
+        }
+        prof[h][r] = (int)w;
+        nuA[h][r] = -i * ge;  // Hb(i, j) of H = 0, also Hb(i, 0)
+        bvA[h][r] = kNeg32;
+        bjA[h][r] = 0;
+      }
+    int32_t B0 = -i0 * ge, B1 = -(i0 + HB) * ge;  // offsets: Hb of each half's top row at column 0
+    int hl[2], f[2], nu[2], bvr[2];
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      hl[r] = pack16(sat16(nuA[0][r] - B0), sat16(nuA[1][r] - B1));
+      f[r] = pack16(kNeg16, kNeg16);
+      nu[r] = hl[r];
+      bvr[r] = pack16(kNeg16, kNeg16);
+    }
+    int diag = pack16(sat16(-(i0 + 2 * lane) * ge - B0), sat16(-(i0 + HB + 2 * lane) * ge - B1));
+    int bot_h = 0, bot_e = pack16(kNeg16, kNeg16), cur_c = 0, out_h = 0, out_e = 0;
+    const int go2 = pack16(go, go), ge2 = pack16(ge, ge), goe2 = pack16(goe, goe);
+    bool failed = false;
+    int2* __restrict__ rin = ring[wib];
+    int2* __restrict__ rout = ring[wib + 1];
+    int2* __restrict__ dl = dline[wib];
+    const bool has_out = b + 1 < nb;
+    auto letter_raw = [&](int col) -> int { return (col >= 1 && col <= m) ? (int)s[col - 1] : -1; };
+    auto letter_idx = [&](int c) -> int {
+      if (c < 0) return 0;
+      if (c >= P.alphabet) {
+        bad = true;
+        c = 0;
+      }
+      return c * 8;
+    };
+    int cn0 = lane < BLK ? letter_raw(1 + lane) : -1;
+    int cn1 = lane < BLK ? letter_raw(1 + lane - D) : -1;
+
+    const int steps = m + 63 + D;  // lane 63's lower half reaches column m at step m + 62 + D
+    for (int tb = 0; tb < steps; tb += BLK) {
+      const int col0 = tb + 1 + lane, col1 = col0 - D;  // lane-0 input columns of the two halves
+      const int c0 = letter_idx(cn0), c1 = letter_idx(cn1);
+      asm volatile("" ::"v"(c0), "v"(c1) : "memory");
+      cn0 = lane < BLK ? letter_raw(col0 + BLK) : -1;
+      cn1 = lane < BLK ? letter_raw(col1 + BLK) : -1;
+      int32_t th0 = 0, te0 = kNeg32, th1 = 0, te1 = kNeg32;
+      if (b > 0) {
+        const int need = min(tb + BLK, m);
+        if (!lds_wait_ge(&pub[wib], need)) {
+          failed = true;
+          break;
+        }
+        if (lane < BLK && col0 <= m) {
+          const int2 v = rin[col0 % kRing];
+          th0 = v.x;
+          te0 = v.y;
+        }
+        asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+        if (lane == 0) __hip_atomic_store(&con[wib], need, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      }
+      if (lane < BLK && col1 >= 1 && col1 <= m) {
+        const int2 v = dl[col1 % kDelayRing];
+        th1 = v.x;
+        te1 = v.y;
+      }
+      // re-base each half on its top-row score at the block's first column while it is in the matrix
+      const int nB0 = (tb + 1 <= m) ? __builtin_amdgcn_readfirstlane(th0) : B0;
+      const int nB1 = (tb + 1 - D >= 1 && tb + 1 - D <= m) ? __builtin_amdgcn_readfirstlane(th1) : B1;
+      if (nB0 != B0 || nB1 != B1) {
+        const int dd = pack16(sat16(nB0 - B0), sat16(nB1 - B1));
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+          hl[r] = psub(hl[r], dd);
+          f[r] = psub(f[r], dd);
+        }
+        bot_h = psub(bot_h, dd);
+        bot_e = psub(bot_e, dd);
+        diag = psub(diag, dd);
+        B0 = nB0;
+        B1 = nB1;
+      }
+      {
+        // floors (see raise_local_floors): the best of both halves' top-row inputs and recorded optima
+        int v = max(th0 + i0 * ge, th1 + (i0 + HB) * ge);
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+          for (int r = 0; r < 2; ++r) v = max(v, bvA[h][r] - nuA[h][r]);
+        const int fl = __ockl_wfred_max_i32(v) - 1;
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+          for (int r = 0; r < 2; ++r) bvA[h][r] = max(bvA[h][r], fl + nuA[h][r]);
+      }
+#pragma unroll
+      for (int r = 0; r < 2; ++r) {
+        nu[r] = pack16(sat16(nuA[0][r] - B0), sat16(nuA[1][r] - B1));
+        bvr[r] = pack16(sat16(bvA[0][r] - B0), sat16(bvA[1][r] - B1));
+      }
+      if (lane < BLK) {
+        st_h[lane] = pack16(sat16(th0 - B0), sat16(th1 - B1));
+        st_e[lane] = pack16(sat16(te0 - B0), sat16(te1 - B1));
+        st_c[lane] = c0 | (c1 << 16);
+      }
+      // One step: lane l relaxes its two rows of each half, the upper at column j = tt - l + 1 and the
+      // lower at j - D.  Near the matrix edges (CK) a half outside it keeps its state unchanged.
+      auto step = [&](int tt, int in_top_h, int in_top_e, int in_top_c, auto checked, int* hk) {
+        constexpr bool CK = decltype(checked)::value;
+        const int j0 = tt - lane + 1, j1 = j0 - D;
+        const int in_h = dpp_shr1(in_top_h, bot_h);
+        const int in_e = dpp_shr1(in_top_e, bot_e);
+        const int in_c = dpp_shr1(in_top_c, cur_c);
+        cur_c = in_c;
+        const int c1s = (int)((uint32_t)in_c >> 16);
+        const bool ok0 = !CK || (j0 >= 1 && j0 <= m), ok1 = !CK || (j1 >= 1 && j1 <= m);
+        const int keep = (ok0 ? 0 : 0xffff) | (ok1 ? 0 : (int)0xffff0000u);  // bits left unchanged
+        auto sel = [&](int old, int nw) { return CK ? ((keep & old) | (~keep & nw)) : nw; };
+        int hd = diag, hup = in_h, eup = in_e;
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+          const int hlo = hl[r];
+          const int e = AFFINE ? pmax(eup, padd(hup, go2)) : hup;
+          const int ff = AFFINE ? pmax(padd(f[r], ge2), padd(hlo, goe2)) : padd(hlo, ge2);
+          // sigma - ge of both halves' cells: the low bytes of two bit-field extracts, side by side
+          const int sg = (int)__builtin_amdgcn_perm((uint32_t)__builtin_amdgcn_sbfe(prof[1][r], c1s, 8),
+                                                    (uint32_t)__builtin_amdgcn_sbfe(prof[0][r], in_c, 8), 0x05040100u);
+          const int d = padd(hd, sg);
+          const int h = pmax(pmax(d, pmax(e, ff)), nu[r]);
+          if (CK) {
+            // exact cell-by-cell optimum tracking, per half
+            const int v0 = lo16(h), v1 = hi16(h);
+            if (ok0 && v0 > lo16(bvr[r])) {
+              bvA[0][r] = v0 + B0;
+              bjA[0][r] = j0;
+              bvr[r] = pack16(v0, hi16(bvr[r]));
+            }
+            if (ok1 && v1 > hi16(bvr[r])) {
+              bvA[1][r] = v1 + B1;
+              bjA[1][r] = j1;
+              bvr[r] = pack16(lo16(bvr[r]), v1);
+            }
+          } else {
+            hk[r] = h;
+          }
+          f[r] = sel(f[r], ff);
+          hl[r] = sel(hlo, h);
+          hd = hlo;
+          hup = h;
+          eup = e;
+        }
+        bot_h = sel(bot_h, hup);
+        bot_e = sel(bot_e, eup);
+        diag = sel(diag, in_h);
+        out_h = dpp_shl1(bot_h, out_h);
+        out_e = dpp_shl1(bot_e, out_e);
+      };
+      for (int g4 = 0; g4 < BLK / 4; ++g4) {
+        const int t0 = tb + 4 * g4;
+        const int4 vh = reinterpret_cast<const int4*>(st_h)[g4];
+        const int4 ve = reinterpret_cast<const int4*>(st_e)[g4];
+        const int4 vc = reinterpret_cast<const int4*>(st_c)[g4];
+        if (t0 >= 63 + D && t0 + 3 < m) {
+          // both halves of every lane inside the matrix: optima tracked per 4 steps
+          int hk[4][2];
+          step(t0, vh.x, ve.x, vc.x, std::false_type(), hk[0]);
+          step(t0 + 1, vh.y, ve.y, vc.y, std::false_type(), hk[1]);
+          step(t0 + 2, vh.z, ve.z, vc.z, std::false_type(), hk[2]);
+          step(t0 + 3, vh.w, ve.w, vc.w, std::false_type(), hk[3]);
+          int mk[2];
+          bool imp = false;
+#pragma unroll
+          for (int r = 0; r < 2; ++r) {
+            mk[r] = pmax(pmax(hk[0][r], hk[1][r]), pmax(hk[2][r], hk[3][r]));
+            imp |= pmax(mk[r], bvr[r]) != bvr[r];
+          }
+          if (imp) {
+#pragma unroll
+            for (int r = 0; r < 2; ++r) {
+#pragma unroll
+              for (int h = 0; h < 2; ++h) {
+                auto half = [&](int x) { return h ? hi16(x) : lo16(x); };
+                const int mv = half(mk[r]);
+                int k = half(hk[2][r]) == mv ? 2 : 3;
+                k = half(hk[1][r]) == mv ? 1 : k;
+                k = half(hk[0][r]) == mv ? 0 : k;
+                const bool up = mv > half(bvr[r]);
+                bjA[h][r] = lane_select(up, t0 - lane + 1 - (h ? D : 0) + k, bjA[h][r]);
+                bvA[h][r] = max(bvA[h][r], mv + (h ? B1 : B0));
+              }
+              bvr[r] = pmax(bvr[r], mk[r]);
+            }
+          }
+        } else {
+          step(t0, vh.x, ve.x, vc.x, std::true_type(), nullptr);
+          step(t0 + 1, vh.y, ve.y, vc.y, std::true_type(), nullptr);
+          step(t0 + 2, vh.z, ve.z, vc.z, std::true_type(), nullptr);
+          step(t0 + 3, vh.w, ve.w, vc.w, std::true_type(), nullptr);
+        }
+      }
+      // lanes 64-BLK.. hold lane 63's outputs of steps tb..tb+BLK-1: the upper half's bottom row at
+      // columns step - 62 (kept for the lower half) and the band's bottom row at step - 62 - D
+      const int so = tb + (lane - (64 - BLK));
+      const bool inw = lane >= 64 - BLK;
+      const int cu = so - 62, cl = so - 62 - D;
+      if (inw && cu >= 1 && cu <= m) dl[cu % kDelayRing] = make_int2(unrel16(lo16(out_h), B0), unrel16(lo16(out_e), B0));
+      if (has_out) {
+        const int hi = min(tb + BLK - 63 - D, m);
+        if (hi >= 1) {
+          if (!lds_wait_ge(&con[wib + 1], hi - kRing)) {  // the band below has read what this overwrites
+            failed = true;
+            break;
+          }
+          if (inw && cl >= 1 && cl <= m)
+            rout[cl % kRing] = make_int2(unrel16(hi16(out_h), B1), unrel16(hi16(out_e), B1));
+          asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+          if (lane == 0) __hip_atomic_store(&pub[wib + 1], hi, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
+      }
+    }
+
+    // band optimum: (score, i, j) over this lane's rows, then across the wave
+    int bs = kNeg32, bi = 0, bjj = 0;
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int r = 0; r < 2; ++r) {
+        const int i = i0 + h * HB + 2 * lane + r + 1;
+        if (i > n) continue;
+        const int sc = bvA[h][r] + i * ge;
+        const int jj = bjA[h][r];
+        const int ci = flip ? jj : i, cj = flip ? i : jj;
+        if (sc > 0 && better(sc, ci, cj, bs, bi, bjj)) {
+          bs = sc;
+          bi = ci;
+          bjj = cj;
+        }
+      }
+    for (int o = 32; o >= 1; o >>= 1) {
+      const int s2_ = __shfl_xor(bs, o, 64), i2 = __shfl_xor(bi, o, 64), j2 = __shfl_xor(bjj, o, 64);
+      if (better(s2_, i2, j2, bs, bi, bjj)) {
+        bs = s2_;
+        bi = i2;
+        bjj = j2;
+      }
+    }
+    const bool anybad = __any(bad);
+    if (lane == 0) W.band_res[t] = make_int4(bs, bi, bjj, (anybad ? 1 : 0) | (failed ? 2 : 0));
+  };
+
   for (;;) {
     if (threadIdx.x == 0) {
       s_t0 = (int64_t)atomicAdd(reinterpret_cast<unsigned long long*>(W.ticket), (unsigned long long)kWfWavesPerBlock);
@@ -594,6 +910,9 @@ __global__ __launch_bounds__(kWfBlock) void wf_i32_group_kernel(const KParams P,
     if (!launch_err && wib == kWfWavesPerBlock) {
       courier(t0g);
     } else if (!launch_err && t0g + wib < n_items) {
+    if constexpr (P16) {
+      p16_band(t0g + wib);
+    } else {
     const int64_t t = t0g + wib;
     const WfPair pr = W.pairs[np == 1 ? 0 : W.item_pair[t]];
     const int b = (int)(t - pr.item0);
@@ -884,6 +1203,7 @@ __global__ __launch_bounds__(kWfBlock) void wf_i32_group_kernel(const KParams P,
     const bool anybad = __any(bad);
     if (lane == 0) W.band_res[t] = make_int4(bs, bi, bjj, (anybad ? 1 : 0) | (failed ? 2 : 0));
     }
+    }
     __syncthreads();  // the group's rings and ticket are reused by the next group
   }
 }
@@ -1024,14 +1344,32 @@ __global__ void wf_single_pair_kernel(WfWs W, int n, int m, int band_rows) {
   }
 }
 
+// Packed 16-bit bands are exact when a block's scores stay within int16 of its offsets: a block's
+// cells lie within 128 rows and 63 + 32 columns of the offset's cell, adjacent cells differ by at most
+// max|sigma| + |go| + 2|ge| (row bias included), and E, F lie within |go + ge| of a neighbouring H.
+// Bounding that step by 32 keeps every value of a block within 26,000 of its offset, clear of the
+// -32,768 that stands for -infinity.
+bool p16_exact(const KParams& kp) {
+  const int64_t smax = kp.sigma_max > -kp.sigma_min ? kp.sigma_max : -(int64_t)kp.sigma_min;
+  const int64_t step = smax - kp.go - 2 * (int64_t)kp.ge;
+  return step <= 32;
+}
+
 template <int MODE, bool AFFINE, int PROF, bool TB>
 void launch_wf_t(const KParams& kp, const uint8_t* q, const uint8_t* s, const WfWs& W, int n_waves, bool grouped,
-                 hipStream_t stream) {
+                 bool p16, hipStream_t stream) {
   const int blocks = (n_waves + kWfWavesPerBlock - 1) / kWfWavesPerBlock;
   const size_t lds = PROF == kProfLane ? (size_t)kWfWavesPerBlock * kp.alphabet * 64 * sizeof(uint32_t) : 0;
+  constexpr bool kCanPack = MODE == ALN_LOCAL && PROF == kProfReg && !TB;
+  if (kCanPack && grouped && p16 && p16_exact(kp)) {
+    ProfScope prof("wavefront_p16", stream);
+    hipLaunchKernelGGL((wf_i32_group_kernel<MODE, AFFINE, PROF, TB, kWfR, kCanPack>), dim3(blocks), dim3(kWfBlock),
+                       lds, stream, kp, q, s, W);
+    return;
+  }
   ProfScope prof(TB ? "wavefront_i32_traceback" : "wavefront_i32", stream);
   if (grouped)
-    hipLaunchKernelGGL((wf_i32_group_kernel<MODE, AFFINE, PROF, TB, kWfR>), dim3(blocks), dim3(kWfBlock), lds,
+    hipLaunchKernelGGL((wf_i32_group_kernel<MODE, AFFINE, PROF, TB, kWfR, false>), dim3(blocks), dim3(kWfBlock), lds,
                        stream, kp, q, s, W);
   else
     hipLaunchKernelGGL((wf_i32_kernel<MODE, AFFINE, PROF, TB, kWfR>), dim3(blocks), dim3(kWfBlockAlone), lds,
@@ -1039,34 +1377,34 @@ void launch_wf_t(const KParams& kp, const uint8_t* q, const uint8_t* s, const Wf
 }
 
 template <int MODE, bool AFFINE, bool TB>
-void launch_wf_p(const KParams& kp, const uint8_t* q, const uint8_t* s, const WfWs& W, int nw, bool grouped,
+void launch_wf_p(const KParams& kp, const uint8_t* q, const uint8_t* s, const WfWs& W, int nw, bool grouped, bool p16,
                  hipStream_t st) {
   const bool bytes = kp.sigma_max - kp.ge <= 127 && kp.sigma_min - kp.ge >= -127;
   if (bytes && kp.alphabet <= 4)
-    launch_wf_t<MODE, AFFINE, kProfReg, TB>(kp, q, s, W, nw, grouped, st);
+    launch_wf_t<MODE, AFFINE, kProfReg, TB>(kp, q, s, W, nw, grouped, p16, st);
   else if (bytes)
-    launch_wf_t<MODE, AFFINE, kProfLane, TB>(kp, q, s, W, nw, grouped, st);
+    launch_wf_t<MODE, AFFINE, kProfLane, TB>(kp, q, s, W, nw, grouped, false, st);
   else
-    launch_wf_t<MODE, AFFINE, kProfTable, TB>(kp, q, s, W, nw, grouped, st);
+    launch_wf_t<MODE, AFFINE, kProfTable, TB>(kp, q, s, W, nw, grouped, false, st);
 }
 
 template <int MODE, bool TB>
-void launch_wf_m(const KParams& kp, const uint8_t* q, const uint8_t* s, const WfWs& W, int nw, bool grouped,
+void launch_wf_m(const KParams& kp, const uint8_t* q, const uint8_t* s, const WfWs& W, int nw, bool grouped, bool p16,
                  hipStream_t st) {
   if (kp.go != 0)
-    launch_wf_p<MODE, true, TB>(kp, q, s, W, nw, grouped, st);
+    launch_wf_p<MODE, true, TB>(kp, q, s, W, nw, grouped, p16, st);
   else
-    launch_wf_p<MODE, false, TB>(kp, q, s, W, nw, grouped, st);
+    launch_wf_p<MODE, false, TB>(kp, q, s, W, nw, grouped, p16, st);
 }
 
 template <int MODE>
 void launch_wf_mode(const KParams& kp, const uint8_t* q, const uint8_t* s, const WfWs& W, int nw, bool grouped, bool tb,
-                    aln_result_t* out, uint32_t* cigar, int64_t cap, hipStream_t st) {
+                    bool p16, aln_result_t* out, uint32_t* cigar, int64_t cap, hipStream_t st) {
   if (tb) {
-    launch_wf_m<MODE, true>(kp, q, s, W, nw, grouped, st);
+    launch_wf_m<MODE, true>(kp, q, s, W, nw, grouped, false, st);
     hipLaunchKernelGGL((wf_finish_kernel<MODE, true>), dim3(256), dim3(256), 0, st, kp, W, out, cigar, cap);
   } else {
-    launch_wf_m<MODE, false>(kp, q, s, W, nw, grouped, st);
+    launch_wf_m<MODE, false>(kp, q, s, W, nw, grouped, p16, st);
     hipLaunchKernelGGL((wf_finish_kernel<MODE, false>), dim3(256), dim3(256), 0, st, kp, W, out, cigar, cap);
   }
 }
@@ -1117,18 +1455,18 @@ WfWs wf_view(void* base_, const WfOffsets& o) {
 }
 
 aln_status_t launch_wf_i32(const KParams& kp, const WfWs& W, const uint8_t* q, const uint8_t* s,
-                           aln_result_t* out, int max_waves, bool grouped, bool tb, uint32_t* cigar,
+                           aln_result_t* out, int max_waves, bool grouped, bool tb, bool p16, uint32_t* cigar,
                            int64_t cigar_cap, hipStream_t stream) {
   hipLaunchKernelGGL(wf_reset_kernel, dim3(256), dim3(256), 0, stream, W);
   switch (kp.mode) {
     case ALN_GLOBAL:
-      launch_wf_mode<ALN_GLOBAL>(kp, q, s, W, max_waves, grouped, tb, out, cigar, cigar_cap, stream);
+      launch_wf_mode<ALN_GLOBAL>(kp, q, s, W, max_waves, grouped, tb, p16, out, cigar, cigar_cap, stream);
       break;
     case ALN_LOCAL:
-      launch_wf_mode<ALN_LOCAL>(kp, q, s, W, max_waves, grouped, tb, out, cigar, cigar_cap, stream);
+      launch_wf_mode<ALN_LOCAL>(kp, q, s, W, max_waves, grouped, tb, p16, out, cigar, cigar_cap, stream);
       break;
     default:
-      launch_wf_mode<ALN_SEMIGLOBAL>(kp, q, s, W, max_waves, grouped, tb, out, cigar, cigar_cap, stream);
+      launch_wf_mode<ALN_SEMIGLOBAL>(kp, q, s, W, max_waves, grouped, tb, p16, out, cigar, cigar_cap, stream);
       break;
   }
   return hipGetLastError() == hipSuccess ? ALN_OK : ALN_E_DEVICE;
@@ -1159,7 +1497,7 @@ aln_status_t launch_long(const KParams& kp, const LongPlan& pl, const uint8_t* q
   hipLaunchKernelGGL(wf_single_pair_kernel, dim3(1), dim3(64), 0, stream, W, (int)n, (int)m, kWfBand);
   // one pair: its bands are few per SIMD, so the grouped engine (no device-memory stalls in the
   // compute waves) is the faster one
-  return launch_wf_i32(kp, W, q, s, out, pl.n_waves, true, pl.tb, cigar, cigar_cap, stream);
+  return launch_wf_i32(kp, W, q, s, out, pl.n_waves, true, pl.tb, false, cigar, cigar_cap, stream);
 }
 
 }  // namespace mialign

@@ -6,7 +6,9 @@ The choices (aln_batch_config_t) decide how a batch is laid out on the GPU, neve
   wf_waves_per_cu  how many persistent waves the wavefront engine keeps per compute unit;
   wf_orient        whether a wavefront pair runs with its longer sequence along the band rows;
   small_bits       packed 16-bit lanes (two pairs per lane, with the exact overflow check and 32-bit
-                   redo) or 32-bit lanes for the one-pair-per-lane kernels.
+                   redo) or 32-bit lanes for the one-pair-per-lane kernels;
+  wf_bits          packed 16-bit cells (two half bands per lane, per-block offsets) or 32-bit lanes for
+                   grouped score-only local wavefront bands.
 Every candidate gives bit-identical results (the parity tests run the same pairs under several configs),
 so the tuner compares time only.  It searches one coordinate at a time from the library's defaults,
 timing the caller's own batch on the caller's stream with HIP events, and caches the winner under a
@@ -31,8 +33,9 @@ SEARCH = (
     ("wf_group", (1, 4)),
     ("wf_orient", (2, 1, -1)),
     ("small_bits", (16, 32)),
+    ("wf_bits", (32, 16)),
 )
-START = dict(wf_min_cells=1 << 16, wf_waves_per_cu=16, wf_orient=-1, small_bits=16, wf_group=0)
+START = dict(wf_min_cells=1 << 16, wf_waves_per_cu=16, wf_orient=-1, small_bits=16, wf_group=0, wf_bits=32)
 # One lane runs a pair's whole matrix in the one-pair-per-lane kernels: thresholds that would leave
 # pairs above this many cells there are not tried (a single such pair takes tens of milliseconds).
 LANE_CELLS_MAX = 1 << 22

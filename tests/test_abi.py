@@ -64,12 +64,18 @@ def test_batch_config_validation_on_host():
         st = aln.lib().aln_align_batch_ex(ctypes.byref(sc), 0, None, None, None, None, 0, 0, 0, 0, 0, ctypes.byref(c),
                                           None, None, None, None, 0, None)
         assert st == e, (cfg, st)
-    c = aln.BatchConfig(wf_group=2).c()
-    st = aln.lib().aln_align_batch_ex(ctypes.byref(sc), 0, None, None, None, None, 0, 0, 0, 0, 0, ctypes.byref(c),
-                                      None, None, None, None, 0, None)
-    assert st == -1
+    for bad in (aln.BatchConfig(wf_group=2), aln.BatchConfig(wf_bits=8)):
+        c = bad.c()
+        st = aln.lib().aln_align_batch_ex(ctypes.byref(sc), 0, None, None, None, None, 0, 0, 0, 0, 0, ctypes.byref(c),
+                                          None, None, None, None, 0, None)
+        assert st == -1, bad
+    for ok in (aln.BatchConfig(wf_bits=16), aln.BatchConfig(wf_bits=32)):
+        c = ok.c()
+        st = aln.lib().aln_align_batch_ex(ctypes.byref(sc), 0, None, None, None, None, 0, 0, 0, 0, 0, ctypes.byref(c),
+                                          None, None, None, None, 0, None)
+        assert st == 0, ok
     c = aln.BatchConfig().c()
-    c.reserved[1] = 5
+    c.reserved = 5
     st = aln.lib().aln_align_batch_ex(ctypes.byref(sc), 0, None, None, None, None, 0, 0, 0, 0, 0, ctypes.byref(c),
                                       None, None, None, None, 0, None)
     assert st == -1

@@ -174,7 +174,7 @@ WF_SCHEMES = {
 @pytest.mark.parametrize("mode", [0, 1, 2], ids=["global", "local", "semi"])
 @pytest.mark.parametrize("scheme", list(WF_SCHEMES))
 @pytest.mark.parametrize("orient", [1, -1, 2], ids=["oriented", "as_given", "cheaper"])
-@pytest.mark.parametrize("group", [1, 4], ids=["alone", "grouped"])
+@pytest.mark.parametrize("group", [1, 4, 416], ids=["alone", "grouped", "grouped_packed16"])
 def test_wavefront_every_pair(gpu, mode, scheme, orient, group):
     """Every non-empty pair on the band wavefront (wf_min_cells = 1), lengths log-uniform 1..1500 in both
     directions, so that pairs run transposed (orient = 1, the longer sequence along the rows) or as given;
@@ -190,7 +190,10 @@ def test_wavefront_every_pair(gpu, mode, scheme, orient, group):
     q, qo = synth.pack(qs)
     s, so = synth.pack(ss)
     w = synth.Workload("wf_" + scheme, mode, A, go, ge, q, qo, s, so, match=ma, mismatch=mi, subst=sub)
-    cfg = aln.BatchConfig(wf_min_cells=1, wf_orient=orient, wf_group=group)
+    if group == 416 and mode != 1:
+        pytest.skip("packed 16-bit bands are local-only")
+    cfg = aln.BatchConfig(wf_min_cells=1, wf_orient=orient, wf_group=4 if group == 416 else group,
+                          wf_bits=16 if group == 416 else 32)
     gres, _ = run_gpu(w, aln.SCORE_ONLY, config=cfg)
     ores, _ = run_oracle(w, False)
     bad = compare(w, gres, None, ores, None, "wf/%s/%d" % (scheme, orient))
@@ -199,7 +202,7 @@ def test_wavefront_every_pair(gpu, mode, scheme, orient, group):
 
 @pytest.mark.parametrize("go", [0, -3], ids=["linear", "affine"])
 @pytest.mark.parametrize("orient", [1, -1], ids=["oriented", "as_given"])
-@pytest.mark.parametrize("group", [1, 4], ids=["alone", "grouped"])
+@pytest.mark.parametrize("group", [1, 4, 416], ids=["alone", "grouped", "grouped_packed16"])
 @pytest.mark.parametrize("tb", [False, True], ids=["score", "traceback"])
 def test_wavefront_local_ties_across_bands(gpu, go, orient, group, tb):
     """Local optima that tie across band boundaries (bands of 256 rows).  Runs of one letter score
@@ -224,11 +227,61 @@ def test_wavefront_local_ties_across_bands(gpu, go, orient, group, tb):
     s, so = synth.pack([b for _, b in pairs])
     w = synth.Workload("ties_bands", 1, 4, go, -1, q, qo, s, so, match=2, mismatch=-3)
     flags = aln.TRACEBACK if tb else aln.SCORE_ONLY
-    cfg = aln.BatchConfig(wf_min_cells=1, wf_orient=orient, wf_group=group)
+    if group == 416 and tb:
+        pytest.skip("packed 16-bit bands are score-only")
+    cfg = aln.BatchConfig(wf_min_cells=1, wf_orient=orient, wf_group=4 if group == 416 else group,
+                          wf_bits=16 if group == 416 else 32)
     gres, gcig = run_gpu(w, flags, config=cfg)
     ores, ocig = run_oracle(w, tb)
     bad = compare(w, gres, gcig if tb else None, ores, ocig if tb else None, "ties/%d/%d" % (orient, group))
     assert not bad, "\n".join(bad[:10])
+
+
+PACKED_SCHEMES = {
+    # (alphabet, match, mismatch, gap_open, gap_extend): the step bound max|sigma| + |go| + 2|ge| is
+    # 7, 32 (the largest the packed bands take) and 5 (linear gaps)
+    "dna": (4, 2, -3, -3, -1),
+    "at_bound": (4, 10, -10, -12, -5),
+    "linear": (4, 3, -2, 0, -1),
+}
+
+
+@pytest.mark.parametrize("scheme", list(PACKED_SCHEMES))
+@pytest.mark.parametrize("orient", [1, -1], ids=["oriented", "as_given"])
+def test_wavefront_packed16(gpu, scheme, orient):
+    """Grouped score-only local bands in packed 16-bit cells (wf_bits = 16) against the oracle and
+    against the 32-bit bands: related pairs long enough that scores pass 32,767 (only the per-block
+    offsets keep the cells in 16 bits), pairs shorter than a half band (128 rows), between a half and
+    a band, of several bands, and unrelated pairs whose optima stay small."""
+    import paper_2002_04561_amd as aln
+    A, ma, mi, go, ge = PACKED_SCHEMES[scheme]
+    rng = np.random.default_rng(5200 + len(scheme) * 3 + (orient > 0))
+    lens = [(20000, 19000), (19000, 20000), (100, 900), (129, 700), (200, 300), (256, 256), (257, 600),
+            (3000, 2500), (1, 500), (500, 1), (127, 128), (640, 5000)]
+    lens += [tuple(int(x) for x in rng.integers(1, 3000, 2)) for _ in range(20)]
+    qs, ss = [], []
+    for k, (a, b) in enumerate(lens):
+        x = rng.integers(0, A, a, dtype=np.uint8)
+        if k % 3 != 2:
+            y = synth.mutate_geometric(rng, x, 0.04, 0.01, 2.0, A)[:b]
+            if len(y) < b:
+                y = np.concatenate([y, rng.integers(0, A, b - len(y), dtype=np.uint8)])
+        else:
+            y = rng.integers(0, A, b, dtype=np.uint8)
+        qs.append(x)
+        ss.append(y)
+    q, qo = synth.pack(qs)
+    s, so = synth.pack(ss)
+    w = synth.Workload("packed16_" + scheme, 1, A, go, ge, q, qo, s, so, match=ma, mismatch=mi)
+    cfg = dict(wf_min_cells=1, wf_orient=orient, wf_group=4)
+    gres, _ = run_gpu(w, aln.SCORE_ONLY, config=aln.BatchConfig(wf_bits=16, **cfg))
+    ores, _ = run_oracle(w, False)
+    bad = compare(w, gres, None, ores, None, "p16/%s/%d" % (scheme, orient))
+    assert not bad, "\n".join(bad[:10])
+    assert int(ores["score"][0]) > 32767  # the first pair's optimum does not fit 16 bits
+    g32, _ = run_gpu(w, aln.SCORE_ONLY, config=aln.BatchConfig(wf_bits=32, **cfg))
+    for f in ("score", "q_end", "s_end", "flags"):
+        assert np.array_equal(gres[f], g32[f]), f
 
 
 @pytest.mark.parametrize("waves", [1, 4, 16, 32])
