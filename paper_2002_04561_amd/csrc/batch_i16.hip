@@ -52,6 +52,11 @@ __device__ __forceinline__ s2 mad_u(s2 a, s2 b, s2 c) {
   return __builtin_bit_cast(s2, r);
 }
 
+// Shorts between consecutive pair slots' profiles: the profile (AP letters x R rows) plus one 32-bit
+// word, so the stride is an odd number of words and the lanes of a wave read their profile words from
+// distinct LDS banks (a stride of whole bank sweeps would put every lane on the same bank).
+__host__ __device__ constexpr int i16_lane_stride(int AP, int R) { return AP * R + 2; }
+
 __device__ __forceinline__ bool fits16(const KParams& P, int n, int m) {
   const int mn = n < m ? n : m;
   const long long up = (long long)mn * (P.sigma_max > 0 ? P.sigma_max : 0);
@@ -89,13 +94,14 @@ __global__ __launch_bounds__(kI16Block) void batch_i16_kernel(
   }
   __syncthreads();
   const int AP = P.alphabet;  // profile letters per pair; past a subject's end, the shared pad row
+  const int LS = i16_lane_stride(AP, R);
   const int lane = threadIdx.x & 63;
   const int wib = threadIdx.x >> 6;
   // per wave: the pad row (R scores of kPadSigma16, the same for every pair), then the profiles
-  short* __restrict__ prof = reinterpret_cast<short*>(smem + kTab * kTab * 4) + (size_t)wib * (R + 128 * AP * R);
+  short* __restrict__ prof = reinterpret_cast<short*>(smem + kTab * kTab * 4) + (size_t)wib * (R + 128 * LS);
   const short* __restrict__ padrow = prof;
-  short* __restrict__ profA = prof + R + (size_t)lane * AP * R;
-  short* __restrict__ profB = prof + R + (size_t)(64 + lane) * AP * R;
+  short* __restrict__ profA = prof + R + (size_t)lane * LS;
+  short* __restrict__ profB = prof + R + (size_t)(64 + lane) * LS;
   if (lane < R) prof[lane] = (short)kPadSigma16;  // read only by this wave, after its own writes
 
   const int64_t wave = (int64_t)blockIdx.x * kI16WavesPerBlock + wib;
@@ -406,7 +412,8 @@ __global__ __launch_bounds__(kI16Block) void batch_i16_kernel(
 template <int MODE, bool AFFINE, bool TB, int R>
 void launch_i16_t(const KParams& kp, const BatchPlan16& pl, const I16Args& a, hipStream_t stream) {
   const int blocks = (pl.n_waves + kI16WavesPerBlock - 1) / kI16WavesPerBlock;
-  const size_t lds = (size_t)kTab * kTab * 4 + (size_t)kI16WavesPerBlock * (R + 128 * kp.alphabet * R) * 2;
+  const size_t lds =
+      (size_t)kTab * kTab * 4 + (size_t)kI16WavesPerBlock * (R + 128 * (size_t)i16_lane_stride(kp.alphabet, R)) * 2;
   ProfScope prof(TB ? "batch_i16_traceback" : "batch_i16_score", stream);
   hipLaunchKernelGGL((batch_i16_kernel<MODE, AFFINE, TB, R>), dim3(blocks), dim3(kI16Block), lds, stream, kp, a.q,
                      a.q_off, a.s, a.s_off, pl.n_pairs, pl.max_n, pl.max_m, a.out, a.cigar, a.cigar_off,
