@@ -96,8 +96,8 @@ __device__ __forceinline__ int lane_select(bool c, int a, int b) {
 // register holds two 16-bit cells: rows of the band's upper half (HB = 128 rows) in its low half and
 // rows of the lower half in its high half, the lower half running kP16Delay steps behind so that the
 // two are independent within a step -- the two halves are independent submatrices sharing one vector
-// lane, as in the paper's inter-task vectorisation (Sec. IV-C), and each keeps its scores as 16-bit
-// differences from an offset of its own, as the paper does within a block (Sec. IV-C): the offset is
+// lane, as in the paper's inter-task vectorisation (Sec. IV-A), and each keeps its scores as 16-bit
+// differences from an offset of its own, as the paper does within a block (Sec. IV-A): the offset is
 // the half's top-row score at the first column of each block of steps.
 typedef short s2 __attribute__((ext_vector_type(2)));
 constexpr int kP16Half = 128;   // rows per half band
