@@ -1209,8 +1209,120 @@ __global__ __launch_bounds__(kWfBlock) void wf_i32_group_kernel(const KParams P,
 }
 
 // One wave per pair: reduces the pair's band optima into its aln_result_t.
-constexpr int kWalkGroups = 16;  // row groups (of kWfR rows) in a traceback window
-constexpr int kWalkCols = 64;    // columns in a traceback window
+constexpr int kWalkGroups = 32;  // row groups (of kWfR rows) in a traceback window
+constexpr int kWalkCols = 128;   // columns in a traceback window
+
+// Traceback of one wavefront pair by a whole wave: the walk of walk_back (the canonical rule of
+// walk.h, which the one-pair-per-lane kernels run per lane), with the codes read from an LDS window of
+// kWalkGroups row groups x kWalkCols columns ending at the current cell, and diagonal runs taken up to
+// 64 cells at a time: lane t looks at cell (i - t, j - t), and the first lane whose cell is not a
+// diagonal move, or lies outside the window or the matrix, ends the run.  Every lane runs the same
+// walk and stores the same runs.  *stuck is set if the walk did not end within 2 (i + j) + 64 turns,
+// which a valid code array never allows.
+template <int MODE>
+__device__ void walk_wave(const uint16_t* __restrict__ codes, int m, int i, int j, uint16_t* __restrict__ win,
+                          int lane, uint32_t* __restrict__ cig, int64_t cap, int* q_begin, int* s_begin, int* n_runs,
+                          bool* stuck) {
+  int g0 = -1, c0 = -1;  // the window holds row groups g0-kWalkGroups+1..g0, columns c0-kWalkCols+1..c0
+  auto inwin = [&](int ii, int jj) -> bool {
+    const int g = (ii - 1) / kWfR;
+    return ii >= 1 && jj >= 1 && g <= g0 && g > g0 - kWalkGroups && jj <= c0 && jj > c0 - kWalkCols;
+  };
+  auto load = [&](int ii, int jj) {
+    g0 = (ii - 1) / kWfR;
+    c0 = jj;
+    // every load of the window is issued before the first LDS write, so the reload costs one
+    // memory latency rather than one per code
+    constexpr int kPer = kWalkGroups * kWalkCols / 64;
+    uint32_t v[kPer];
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const int k = lane + 64 * u;
+      const int gg = g0 - k / kWalkCols, cc = c0 - k % kWalkCols;
+      v[u] = (gg >= 0 && cc >= 1) ? codes[(size_t)gg * (size_t)m + (size_t)(cc - 1)] : 0u;
+    }
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) win[lane + 64 * u] = (uint16_t)v[u];
+    asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)" ::: "memory");  // the window is in LDS before it is read
+  };
+  auto code = [&](int ii, int jj) -> uint32_t {
+    const int g = (ii - 1) / kWfR;
+    const uint32_t w = win[(g0 - g) * kWalkCols + (c0 - jj)];
+    return (w >> (4 * ((ii - 1) % kWfR))) & 15u;
+  };
+  int64_t runs = 0;
+  uint32_t cur_op = 0xffu, cur_len = 0;
+  auto push = [&](uint32_t op, uint32_t len) {
+    if (op == cur_op) {
+      cur_len += len;
+      return;
+    }
+    if (cur_len) {
+      if (runs < cap) cig[runs] = (cur_len << 4) | cur_op;
+      ++runs;
+    }
+    cur_op = op;
+    cur_len = len;
+  };
+  int state = 0;  // 0 = H, 1 = E, 2 = F
+  int64_t turns = 2 * ((int64_t)i + j) + 64;
+  for (; turns > 0; --turns) {
+    if (state == 0) {
+      if (i == 0 || j == 0) {
+        if (MODE == ALN_GLOBAL) {
+          if (j > 0) push(ALN_CIGAR_D, (uint32_t)j);
+          if (i > 0) push(ALN_CIGAR_I, (uint32_t)i);
+          i = 0;
+          j = 0;
+        }
+        break;
+      }
+      if (!inwin(i, j)) load(i, j);
+      bool diag = false;
+      if (inwin(i - lane, j - lane)) diag = (code(i - lane, j - lane) & 3u) == 0u;
+      const unsigned long long stop = __builtin_amdgcn_ballot_w64(!diag);
+      const int k = stop ? __builtin_ctzll(stop) : 64;
+      if (k > 0) {
+        push(ALN_CIGAR_M, (uint32_t)k);
+        i -= k;
+        j -= k;
+        continue;
+      }
+      const uint32_t hs = code(i, j) & 3u;  // (i, j) is in the window: it was loaded above
+      if (hs == 3u) break;
+      state = (int)hs;
+    } else {
+      if (!inwin(i, j)) load(i, j);
+      const uint32_t c = code(i, j);
+      if (state == 1) {
+        push(ALN_CIGAR_I, 1);
+        if (!(c & 4u)) state = 0;
+        --i;
+        if (i == 0) state = 0;
+      } else {
+        push(ALN_CIGAR_D, 1);
+        if (!(c & 8u)) state = 0;
+        --j;
+        if (j == 0) state = 0;
+      }
+    }
+  }
+  *stuck = turns <= 0;
+  if (cur_len) {
+    if (runs < cap) cig[runs] = (cur_len << 4) | cur_op;
+    ++runs;
+  }
+  if (runs <= cap) {
+    for (int64_t a = 0, b = runs - 1; a < b; ++a, --b) {
+      const uint32_t t = cig[a];
+      cig[a] = cig[b];
+      cig[b] = t;
+    }
+  }
+  *q_begin = i;
+  *s_begin = j;
+  *n_runs = (int)runs;
+}
 
 template <int MODE, bool TB>
 __global__ __launch_bounds__(256) void wf_finish_kernel(const KParams P, WfWs W, aln_result_t* __restrict__ out,
@@ -1275,32 +1387,16 @@ __global__ __launch_bounds__(256) void wf_finish_kernel(const KParams P, WfWs W,
     }
     if (TB && r.flags == 0) {
       // The codes form a [row group][column] array of 16-bit words, 4 rows per word (band bb, lane L
-      // is row group bb * 64 + L).  The whole wave walks in lockstep: a window of kWalkGroups row
-      // groups x kWalkCols columns ending at the current cell is loaded into LDS by all lanes, and
-      // the walk reads it there until it steps out of the window.
-      const uint16_t* __restrict__ codes = W.codes + pr.code_off;
-      uint16_t* __restrict__ win = walk_win[threadIdx.x >> 6];
-      int g0 = -1, c0 = -1;  // the window holds row groups g0-kWalkGroups+1..g0, columns c0-kWalkCols+1..c0
-      auto code = [&](int ii, int jj) -> uint32_t {
-        const int g = (ii - 1) / kWfR;
-        if (g > g0 || g <= g0 - kWalkGroups || jj > c0 || jj <= c0 - kWalkCols) {
-          g0 = g;
-          c0 = jj;
-          for (int k = lane; k < kWalkGroups * kWalkCols; k += 64) {
-            const int gg = g0 - k / kWalkCols, cc = c0 - k % kWalkCols;
-            win[k] = (gg >= 0 && cc >= 1) ? codes[(size_t)gg * (size_t)m + (size_t)(cc - 1)] : (uint16_t)0;
-          }
-          asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)" ::: "memory");  // the window is in LDS before it is read
-        }
-        const uint32_t w = win[(g0 - g) * kWalkCols + (c0 - jj)];
-        return (w >> (4 * ((ii - 1) % kWfR))) & 15u;
-      };
+      // is row group bb * 64 + L); walk_wave walks them with the whole wave.
       int qbeg, sbeg, runs;
-      walk_back<MODE>(code, r.q_end, r.s_end, cigar, cigar_cap, &qbeg, &sbeg, &runs);
+      bool stuck = false;
+      walk_wave<MODE>(W.codes + pr.code_off, m, r.q_end, r.s_end, walk_win[threadIdx.x >> 6], lane, cigar, cigar_cap,
+                      &qbeg, &sbeg, &runs, &stuck);
       r.q_begin = qbeg;
       r.s_begin = sbeg;
       r.cigar_len = runs;
       if (runs > cigar_cap) r.flags |= ALN_RES_CIGAR_TRUNC;
+      if (stuck) r.flags |= ALN_RES_DEVICE_ERROR;
     }
     if (lane == 0) out[pr.out_idx] = r;
   }
