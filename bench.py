@@ -314,8 +314,7 @@ def main():
     ap.add_argument("--no-check", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path (see DESIGN.md for how the "
-              "work would shard)", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path", file=sys.stderr)
         sys.exit(2)
 
     if args.copy_calibration:
