@@ -57,7 +57,7 @@ typedef int32_t aln_status_t;
 #define ALN_E_SCORING (-3)     /* gap_open > 0, gap_extend >= 0, or scores too large to be exact */
 #define ALN_E_WORKSPACE (-4)   /* workspace smaller than the size query returned */
 #define ALN_E_DEVICE (-5)      /* a HIP call failed (launch or device query) */
-#define ALN_E_UNSUPPORTED (-6) /* a combination this build does not provide */
+#define ALN_E_UNSUPPORTED (-6) /* a combination the library does not provide */
 
 #define ALN_GLOBAL 0
 #define ALN_LOCAL 1
