@@ -1441,9 +1441,10 @@ __global__ void wf_single_pair_kernel(WfWs W, int n, int m, int band_rows) {
 }
 
 // Packed 16-bit bands are exact when a block's scores stay within int16 of its offsets: a block's
-// cells lie within 128 rows and 63 + 32 columns of the offset's cell, adjacent cells differ by at most
-// max|sigma| + |go| + 2|ge| (row bias included), and E, F lie within |go + ge| of a neighbouring H.
-// Bounding that step by 32 keeps every value of a block within 26,000 of its offset, clear of the
+// cells lie within 128 rows and 63 + 32 columns of the offset's cell, and the block's own 32 steps
+// move the offset's column by at most 32 more; adjacent cells differ by at most max|sigma| + |go| +
+// 2|ge| (row bias included), and E, F lie within |go + ge| of a neighbouring H.  Bounding that step
+// by 32 keeps every value of a block within (128 + 95 + 32) x 32 = 8,160 of its offset, far from the
 // -32,768 that stands for -infinity.
 bool p16_exact(const KParams& kp) {
   const int64_t smax = kp.sigma_max > -kp.sigma_min ? kp.sigma_max : -(int64_t)kp.sigma_min;

@@ -239,10 +239,12 @@ def test_wavefront_local_ties_across_bands(gpu, go, orient, group, tb):
 
 PACKED_SCHEMES = {
     # (alphabet, match, mismatch, gap_open, gap_extend): the step bound max|sigma| + |go| + 2|ge| is
-    # 7, 32 (the largest the packed bands take) and 5 (linear gaps)
+    # 7, 32 (the largest the packed bands take), 5 (linear gaps) and 40 (beyond the bound: wf_bits =
+    # 16 must fall back to 32-bit bands)
     "dna": (4, 2, -3, -3, -1),
     "at_bound": (4, 10, -10, -12, -5),
     "linear": (4, 3, -2, 0, -1),
+    "beyond_bound": (4, 20, -20, -10, -5),
 }
 
 
