@@ -104,6 +104,11 @@ constexpr int kP16Half = 128;   // rows per half band
 constexpr int kP16Delay = 96;   // steps between the upper and the lower half
 constexpr int kDelayRing = 256; // columns of the upper half's bottom row kept for the lower half
 constexpr int kNeg16 = -32768;  // stands for -infinity; sums saturate, so it stays far below real scores
+// The lower half's lane 0 reads columns up to j + kBlkGrouped - 1 - kP16Delay at the start of the block
+// of step j; the upper half's lane 63 has written them by then only if the delay covers a block plus
+// lane 63's 63 steps.  The delay line must also keep a column until the lower half has read it.
+static_assert(kP16Delay >= kBlkGrouped + 63, "the delay between the halves must cover a block and the lanes");
+static_assert(kDelayRing >= kP16Delay + kBlkGrouped, "the delay line must hold the columns in flight");
 
 __device__ __forceinline__ s2 as_s2(int x) { return __builtin_bit_cast(s2, x); }
 __device__ __forceinline__ int as_int(s2 x) { return __builtin_bit_cast(int, x); }
