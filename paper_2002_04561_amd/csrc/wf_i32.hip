@@ -1018,6 +1018,10 @@ __global__ __launch_bounds__(kWfBlock) void wf_i32_group_kernel(const KParams P,
       // so waiting for the old letter must not also wait for the new load
       asm volatile("" ::"v"(sreg) : "memory");
       c_next = lane < BLK ? letter_raw(col_in + BLK) : -1;
+      // The band below's consumption, read together with the input counter: it only grows, so a value
+      // that already allows this block's output spares the wait at the block's end.
+      const int con_seen =
+          has_out ? __hip_atomic_load(&con[wib + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) : 0;
       int32_t th = 0, te = kNeg32;
       if (b == 0) {
         th = (MODE == ALN_GLOBAL) ? go + col_in * ge : 0;
@@ -1147,7 +1151,8 @@ __global__ __launch_bounds__(kWfBlock) void wf_i32_group_kernel(const KParams P,
         const int col_out = tb + (lane - (64 - BLK)) - 62;
         const bool mine = lane >= 64 - BLK && col_out >= 1 && col_out <= m;
         if (hi >= 1) {
-          if (!lds_wait_ge(&con[wib + 1], hi - kRing)) {  // the band below has read what this overwrites
+          // the band below has read what this overwrites
+          if (con_seen < hi - kRing && !lds_wait_ge(&con[wib + 1], hi - kRing)) {
             failed = true;
             break;
           }
