@@ -1226,13 +1226,17 @@ constexpr int kWalkCols = 128;   // columns in a traceback window
 // walk.h, which the one-pair-per-lane kernels run per lane), with the codes read from an LDS window of
 // kWalkGroups row groups x kWalkCols columns ending at the current cell, and diagonal runs taken up to
 // 64 cells at a time: lane t looks at cell (i - t, j - t), and the first lane whose cell is not a
-// diagonal move, or lies outside the window or the matrix, ends the run.  Every lane runs the same
-// walk and stores the same runs.  *stuck is set if the walk did not end within 2 (i + j) + 64 turns,
-// which a valid code array never allows.
+// diagonal move, or lies outside the window or the matrix, ends the run.  Gap runs are taken the same
+// way along their column or row.  Every lane runs the same walk and stores the same runs.  *stuck is
+// set if the walk did not end within 2 (i + j) + 64 turns, which a valid code array never allows.
 template <int MODE>
 __device__ void walk_wave(const uint16_t* __restrict__ codes, int m, int i, int j, uint16_t* __restrict__ win,
                           int lane, uint32_t* __restrict__ cig, int64_t cap, int* q_begin, int* s_begin, int* n_runs,
                           bool* stuck) {
+  // Every lane holds the same walk state; saying so lets the compiler keep it in scalar registers
+  // and branch on it with scalar branches.
+  i = __builtin_amdgcn_readfirstlane(i);
+  j = __builtin_amdgcn_readfirstlane(j);
   int g0 = -1, c0 = -1;  // the window holds row groups g0-kWalkGroups+1..g0, columns c0-kWalkCols+1..c0
   auto inwin = [&](int ii, int jj) -> bool {
     const int g = (ii - 1) / kWfR;
@@ -1243,13 +1247,17 @@ __device__ void walk_wave(const uint16_t* __restrict__ codes, int m, int i, int 
     c0 = jj;
     // every load of the window is issued before the first LDS write, so the reload costs one
     // memory latency rather than one per code
+    // A window cell outside the matrix (row group < 0 or column < 1) loads the in-bounds cell
+    // (g0, c0) instead; inwin() never lets code() read such a cell.  The loads carry no branches,
+    // so all of them stay in flight together.
     constexpr int kPer = kWalkGroups * kWalkCols / 64;
     uint32_t v[kPer];
 #pragma unroll
     for (int u = 0; u < kPer; ++u) {
       const int k = lane + 64 * u;
       const int gg = g0 - k / kWalkCols, cc = c0 - k % kWalkCols;
-      v[u] = (gg >= 0 && cc >= 1) ? codes[(size_t)gg * (size_t)m + (size_t)(cc - 1)] : 0u;
+      const bool ok = gg >= 0 && cc >= 1;
+      v[u] = codes[(size_t)(ok ? gg : g0) * (size_t)m + (size_t)((ok ? cc : c0) - 1)];
     }
 #pragma unroll
     for (int u = 0; u < kPer; ++u) win[lane + 64 * u] = (uint16_t)v[u];
@@ -1288,9 +1296,9 @@ __device__ void walk_wave(const uint16_t* __restrict__ codes, int m, int i, int 
         break;
       }
       if (!inwin(i, j)) load(i, j);
-      bool diag = false;
-      if (inwin(i - lane, j - lane)) diag = (code(i - lane, j - lane) & 3u) == 0u;
-      const unsigned long long stop = __builtin_amdgcn_ballot_w64(!diag);
+      uint32_t pc = 3u;  // a cell outside the window ends the run like a non-diagonal code
+      if (inwin(i - lane, j - lane)) pc = code(i - lane, j - lane);
+      const unsigned long long stop = __builtin_amdgcn_ballot_w64((pc & 3u) != 0u);
       const int k = stop ? __builtin_ctzll(stop) : 64;
       if (k > 0) {
         push(ALN_CIGAR_M, (uint32_t)k);
@@ -1298,23 +1306,43 @@ __device__ void walk_wave(const uint16_t* __restrict__ codes, int m, int i, int 
         j -= k;
         continue;
       }
-      const uint32_t hs = code(i, j) & 3u;  // (i, j) is in the window: it was loaded above
-      if (hs == 3u) break;
-      state = (int)hs;
-    } else {
-      if (!inwin(i, j)) load(i, j);
-      const uint32_t c = code(i, j);
+      // lane 0 looked at (i, j) itself, which the window holds; its code also gives the first gap
+      // step, taken below without reading the cell again
+      const uint32_t c = (uint32_t)__builtin_amdgcn_readfirstlane((int)pc);
+      if ((c & 3u) == 3u) break;
+      state = (int)(c & 3u);
       if (state == 1) {
         push(ALN_CIGAR_I, 1);
-        if (!(c & 4u)) state = 0;
+        if (!(c & 4u) || i == 1) state = 0;
         --i;
-        if (i == 0) state = 0;
       } else {
         push(ALN_CIGAR_D, 1);
-        if (!(c & 8u)) state = 0;
+        if (!(c & 8u) || j == 1) state = 0;
         --j;
-        if (j == 0) state = 0;
       }
+    } else {
+      // A gap run, up to 64 steps at a time: lane t looks at the t-th cell of the run.  The run goes
+      // on through a cell whose extension bit is set and which is not in row (column) 1; the first
+      // cell that ends it is stepped through and returns the walk to H, unless it lies outside the
+      // window, where the walk stops short of it and reloads.
+      if (!inwin(i, j)) load(i, j);
+      const bool vert = state == 1;
+      const int ii = vert ? i - lane : i, jj = vert ? j : j - lane;
+      const bool in = inwin(ii, jj);
+      uint32_t pc = 0u;
+      if (in) pc = code(ii, jj);
+      const bool more = in && (pc & (vert ? 4u : 8u)) != 0u && (vert ? ii : jj) > 1;
+      const unsigned long long stop = __builtin_amdgcn_ballot_w64(!more);
+      const unsigned long long inside = __builtin_amdgcn_ballot_w64(in);
+      const int k = stop ? __builtin_ctzll(stop) : 64;
+      const bool ends = k < 64 && ((inside >> k) & 1ull);
+      const int steps = k + (ends ? 1 : 0);
+      push(vert ? ALN_CIGAR_I : ALN_CIGAR_D, (uint32_t)steps);
+      if (vert)
+        i -= steps;
+      else
+        j -= steps;
+      if (ends) state = 0;
     }
   }
   *stuck = turns <= 0;

@@ -129,6 +129,28 @@ def test_long_traceback_shapes(gpu, mode, gap):
         assert got[:6] == (r.score, r.q_begin, r.q_end, r.s_begin, r.s_end, r.cigar), (n, m)
 
 
+@pytest.mark.parametrize("mode", [0, 1, 2], ids=["global", "local", "semi"])
+@pytest.mark.parametrize("where", ["inner", "leading", "trailing"])
+def test_long_traceback_long_gaps(gpu, mode, where):
+    """Gap runs longer than the 64 cells the traceback walk looks ahead and crossing its 128-cell windows:
+    one side carries an extra stretch of 150 (or 70) letters, in the middle or at either end, so the
+    optimal path takes a long deletion and a long insertion.  At the ends the runs reach row or column 1."""
+    rng = np.random.default_rng(70 + mode)
+    sc = oracle.Scoring.simple(mode, 4, 2, -3, -3, -1)
+    base = rng.integers(0, 4, 600, dtype=np.uint8)
+    extra = rng.integers(0, 4, 150 if where == "inner" else 70, dtype=np.uint8)
+    if where == "inner":
+        longer = np.concatenate([base[:200], extra, base[200:]])
+    elif where == "leading":
+        longer = np.concatenate([extra, base])
+    else:
+        longer = np.concatenate([base, extra])
+    for q, s in ((base, longer), (longer, base)):
+        got = _run_tb(q, s, mode, 4, -3, -1, match=2, mismatch=-3)
+        r = oracle.align(sc, q, s, traceback=True)
+        assert got[:6] == (r.score, r.q_begin, r.q_end, r.s_begin, r.s_end, r.cigar), (len(q), len(s))
+
+
 def test_long_traceback_protein(gpu):
     rng = np.random.default_rng(61)
     sig = synth.protein_sigma(rng)
