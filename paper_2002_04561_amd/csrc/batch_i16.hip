@@ -52,10 +52,18 @@ __device__ __forceinline__ s2 mad_u(s2 a, s2 b, s2 c) {
   return __builtin_bit_cast(s2, r);
 }
 
-// Shorts between consecutive pair slots' profiles: the profile (AP letters x R rows) plus one 32-bit
-// word, so the stride is an odd number of words and the lanes of a wave read their profile words from
-// distinct LDS banks (a stride of whole bank sweeps would put every lane on the same bank).
-__host__ __device__ constexpr int i16_lane_stride(int AP, int R) { return AP * R + 2; }
+// LDS query profile of one wave, in 32-bit words.  For letter c, the R scores of a pair slot are
+// W = R/2 words, cut into chunks of CW words (one ds_read_b128, or b64 when R = 4); chunk k of every
+// slot of a letter lies in one block, [letter][chunk][slot][CW words].  Each letter block spans a
+// whole number of 64-word bank sweeps, so the chunk a lane reads sits in the same banks whatever
+// letter it reads, and the lanes of a read cover the banks once: no bank conflicts.  After the AP
+// letter blocks comes one pad row (the W words of kPadSigma16 pairs that every slot reads past its
+// subject's end, the same address for all lanes), padded to a bank sweep.  The profiles start at a
+// 256-byte boundary after the substitution table.
+constexpr int kI16ProfBase = (kTab * kTab * 4 + 255) & ~255;
+__host__ __device__ constexpr int i16_chunk_words(int R) { return R / 2 < 4 ? R / 2 : 4; }
+__host__ __device__ constexpr int i16_wave_prof_words(int AP, int R) { return AP * 128 * (R / 2) + 64; }
+static_assert(kI16ProfBase % 256 == 0, "profiles start on a bank sweep");
 
 __device__ __forceinline__ bool fits16(const KParams& P, int n, int m) {
   const int mn = n < m ? n : m;
@@ -94,15 +102,14 @@ __global__ __launch_bounds__(kI16Block) void batch_i16_kernel(
   }
   __syncthreads();
   const int AP = P.alphabet;  // profile letters per pair; past a subject's end, the shared pad row
-  const int LS = i16_lane_stride(AP, R);
+  constexpr int W = R / 2, CW = i16_chunk_words(R), NCH = W / CW, SCH = 128 * CW;
+  const int SC = 128 * W;  // words per letter block
   const int lane = threadIdx.x & 63;
   const int wib = threadIdx.x >> 6;
-  // per wave: the pad row (R scores of kPadSigma16, the same for every pair), then the profiles
-  short* __restrict__ prof = reinterpret_cast<short*>(smem + kTab * kTab * 4) + (size_t)wib * (R + 128 * LS);
-  const short* __restrict__ padrow = prof;
-  short* __restrict__ profA = prof + R + (size_t)lane * LS;
-  short* __restrict__ profB = prof + R + (size_t)(64 + lane) * LS;
-  if (lane < R) prof[lane] = (short)kPadSigma16;  // read only by this wave, after its own writes
+  uint32_t* __restrict__ profw =
+      reinterpret_cast<uint32_t*>(smem + kI16ProfBase) + (size_t)wib * i16_wave_prof_words(AP, R);
+  uint32_t* __restrict__ padw = profw + (size_t)AP * SC;
+  if (lane < W) padw[lane] = (0xffffu & (uint32_t)kPadSigma16) | ((uint32_t)kPadSigma16 << 16);  // read by this wave only
 
   const int64_t wave = (int64_t)blockIdx.x * kI16WavesPerBlock + wib;
   char* slab = ws + wave * slab_bytes;
@@ -158,9 +165,9 @@ __global__ __launch_bounds__(kI16Block) void batch_i16_kernel(
 
     for (int k = 0; k < strips; ++k) {
       const int i0 = k * R;
-      // query profile of this strip for both pairs: prof[c*R + r] = sigma(q_{i0+r+1}, c)
+      // query profile of this strip for both pairs: row r of letter c is sigma(q_{i0+r+1}, c)
       for (int h = 0; h < 2; ++h) {
-        short* pr = h ? profB : profA;
+        uint32_t* pr = profw + (size_t)(h * 64 + lane) * CW;
         int qc[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
@@ -177,13 +184,18 @@ __global__ __launch_bounds__(kI16Block) void batch_i16_kernel(
         }
         for (int c = 0; c < AP; ++c) {
           const int cc = c < P.alphabet ? c : kPad;
-          uint32_t w[R / 2 > 0 ? R / 2 : 1];
+          uint32_t w[W];
 #pragma unroll
           for (int r = 0; r < R; r += 2)
             w[r / 2] = (uint32_t)(tab[qc[r] + cc] & 0xffff) | ((uint32_t)tab[qc[r + 1] + cc] << 16);
-          uint32_t* dst = reinterpret_cast<uint32_t*>(pr + c * R);
+          uint32_t* dst = pr + (size_t)c * SC;
 #pragma unroll
-          for (int r = 0; r < R / 2; ++r) dst[r] = w[r];
+          for (int k = 0; k < NCH; ++k) {
+            if constexpr (CW == 4)
+              *reinterpret_cast<uint4*>(dst + k * SCH) = make_uint4(w[4 * k], w[4 * k + 1], w[4 * k + 2], w[4 * k + 3]);
+            else
+              *reinterpret_cast<uint2*>(dst + k * SCH) = make_uint2(w[2 * k], w[2 * k + 1]);
+          }
         }
       }
       s2 hl[R], f[R], bv[R], bjr[R], cap[R];
@@ -228,13 +240,24 @@ __global__ __launch_bounds__(kI16Block) void batch_i16_kernel(
         s2 hup = from_bits(top.x), eup = from_bits(top.y);
         s2 hd = hdiag;
         hdiag = hup;
-        const uint32_t* pa = reinterpret_cast<const uint32_t*>(ca < AP ? profA + ca * R : padrow);
-        const uint32_t* pb = reinterpret_cast<const uint32_t*>(cb < AP ? profB + cb * R : padrow);
-        uint32_t wa[R / 2], wb[R / 2];
+        // chunk k of a slot's letter is SCH words after chunk k-1; the pad row's chunks are adjacent
+        const uint32_t* pa = ca < AP ? profw + (size_t)ca * SC + (size_t)lane * CW : padw;
+        const uint32_t* pb = cb < AP ? profw + (size_t)cb * SC + (size_t)(64 + lane) * CW : padw;
+        const int sa = ca < AP ? SCH : CW, sb2 = cb < AP ? SCH : CW;
+        uint32_t wa[W], wb[W];
 #pragma unroll
-        for (int r = 0; r < R / 2; ++r) {
-          wa[r] = pa[r];
-          wb[r] = pb[r];
+        for (int k = 0; k < NCH; ++k) {
+          if constexpr (CW == 4) {
+            const uint4 va = *reinterpret_cast<const uint4*>(pa + k * sa);
+            const uint4 vb = *reinterpret_cast<const uint4*>(pb + k * sb2);
+            wa[4 * k] = va.x, wa[4 * k + 1] = va.y, wa[4 * k + 2] = va.z, wa[4 * k + 3] = va.w;
+            wb[4 * k] = vb.x, wb[4 * k + 1] = vb.y, wb[4 * k + 2] = vb.z, wb[4 * k + 3] = vb.w;
+          } else {
+            const uint2 va = *reinterpret_cast<const uint2*>(pa + k * sa);
+            const uint2 vb = *reinterpret_cast<const uint2*>(pb + k * sb2);
+            wa[2 * k] = va.x, wa[2 * k + 1] = va.y;
+            wb[2 * k] = vb.x, wb[2 * k + 1] = vb.y;
+          }
         }
         uint32_t acc[RW];
 #pragma unroll
@@ -412,8 +435,7 @@ __global__ __launch_bounds__(kI16Block) void batch_i16_kernel(
 template <int MODE, bool AFFINE, bool TB, int R>
 void launch_i16_t(const KParams& kp, const BatchPlan16& pl, const I16Args& a, hipStream_t stream) {
   const int blocks = (pl.n_waves + kI16WavesPerBlock - 1) / kI16WavesPerBlock;
-  const size_t lds =
-      (size_t)kTab * kTab * 4 + (size_t)kI16WavesPerBlock * (R + 128 * (size_t)i16_lane_stride(kp.alphabet, R)) * 2;
+  const size_t lds = (size_t)kI16ProfBase + (size_t)kI16WavesPerBlock * i16_wave_prof_words(kp.alphabet, R) * 4;
   ProfScope prof(TB ? "batch_i16_traceback" : "batch_i16_score", stream);
   hipLaunchKernelGGL((batch_i16_kernel<MODE, AFFINE, TB, R>), dim3(blocks), dim3(kI16Block), lds, stream, kp, a.q,
                      a.q_off, a.s, a.s_off, pl.n_pairs, pl.max_n, pl.max_m, a.out, a.cigar, a.cigar_off,
