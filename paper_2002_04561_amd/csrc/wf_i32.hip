@@ -1237,19 +1237,21 @@ __device__ void walk_wave(const uint16_t* __restrict__ codes, int m, int i, int 
   // and branch on it with scalar branches.
   i = __builtin_amdgcn_readfirstlane(i);
   j = __builtin_amdgcn_readfirstlane(j);
-  int g0 = -1, c0 = -1;  // the window holds row groups g0-kWalkGroups+1..g0, columns c0-kWalkCols+1..c0
-  auto inwin = [&](int ii, int jj) -> bool {
-    const int g = (ii - 1) / kWfR;
-    return ii >= 1 && jj >= 1 && g <= g0 && g > g0 - kWalkGroups && jj <= c0 && jj > c0 - kWalkCols;
-  };
+  // The window holds row groups g0-kWalkGroups+1..g0 and columns c0-kWalkCols+1..c0; it is loaded at
+  // the walk's cell, in row group g0 and column c0.  The walk only moves up and left, so every later
+  // cell is inside it as long as it lies at or below row ilo and at or right of column jlo (the
+  // window's first row and column inside the matrix).  Before the first load nothing is inside.
+  int g0 = 0, c0 = 0, ilo = 0x7fffffff, jlo = 0x7fffffff;
   auto load = [&](int ii, int jj) {
     g0 = (ii - 1) / kWfR;
     c0 = jj;
+    ilo = max(1, (g0 - kWalkGroups + 1) * kWfR + 1);
+    jlo = max(1, c0 - kWalkCols + 1);
     // every load of the window is issued before the first LDS write, so the reload costs one
     // memory latency rather than one per code
     // A window cell outside the matrix (row group < 0 or column < 1) loads the in-bounds cell
-    // (g0, c0) instead; inwin() never lets code() read such a cell.  The loads carry no branches,
-    // so all of them stay in flight together.
+    // (g0, c0) instead; it lies before row ilo or column jlo, so code() never reads it.  The loads
+    // carry no branches, so all of them stay in flight together.
     constexpr int kPer = kWalkGroups * kWalkCols / 64;
     uint32_t v[kPer];
 #pragma unroll
@@ -1263,10 +1265,11 @@ __device__ void walk_wave(const uint16_t* __restrict__ codes, int m, int i, int 
     for (int u = 0; u < kPer; ++u) win[lane + 64 * u] = (uint16_t)v[u];
     asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)" ::: "memory");  // the window is in LDS before it is read
   };
+  // the code of a cell inside the window
   auto code = [&](int ii, int jj) -> uint32_t {
-    const int g = (ii - 1) / kWfR;
-    const uint32_t w = win[(g0 - g) * kWalkCols + (c0 - jj)];
-    return (w >> (4 * ((ii - 1) % kWfR))) & 15u;
+    const unsigned r = (unsigned)(ii - 1);
+    const uint32_t w = win[(g0 - (int)(r / kWfR)) * kWalkCols + (c0 - jj)];
+    return (w >> (4 * (r % kWfR))) & 15u;
   };
   int64_t runs = 0;
   uint32_t cur_op = 0xffu, cur_len = 0;
@@ -1295,9 +1298,14 @@ __device__ void walk_wave(const uint16_t* __restrict__ codes, int m, int i, int 
         }
         break;
       }
-      if (!inwin(i, j)) load(i, j);
-      uint32_t pc = 3u;  // a cell outside the window ends the run like a non-diagonal code
-      if (inwin(i - lane, j - lane)) pc = code(i - lane, j - lane);
+      if (i < ilo || j < jlo) load(i, j);
+      // lanes t <= lim look at cells inside the window; the others read (i, j) and count as a
+      // non-diagonal code, which ends the run
+      const int lim = min(i - ilo, j - jlo);
+      const bool in = lane <= lim;
+      const int t = in ? lane : 0;
+      const uint32_t ct = code(i - t, j - t);
+      const uint32_t pc = in ? ct : 3u;
       const unsigned long long stop = __builtin_amdgcn_ballot_w64((pc & 3u) != 0u);
       const int k = stop ? __builtin_ctzll(stop) : 64;
       if (k > 0) {
@@ -1325,17 +1333,17 @@ __device__ void walk_wave(const uint16_t* __restrict__ codes, int m, int i, int 
       // on through a cell whose extension bit is set and which is not in row (column) 1; the first
       // cell that ends it is stepped through and returns the walk to H, unless it lies outside the
       // window, where the walk stops short of it and reloads.
-      if (!inwin(i, j)) load(i, j);
+      if (i < ilo || j < jlo) load(i, j);
       const bool vert = state == 1;
-      const int ii = vert ? i - lane : i, jj = vert ? j : j - lane;
-      const bool in = inwin(ii, jj);
-      uint32_t pc = 0u;
-      if (in) pc = code(ii, jj);
+      const int lim = vert ? i - ilo : j - jlo;  // lanes t <= lim look at cells inside the window
+      const bool in = lane <= lim;
+      const int t = in ? lane : 0;
+      const int ii = vert ? i - t : i, jj = vert ? j : j - t;
+      const uint32_t pc = code(ii, jj);
       const bool more = in && (pc & (vert ? 4u : 8u)) != 0u && (vert ? ii : jj) > 1;
       const unsigned long long stop = __builtin_amdgcn_ballot_w64(!more);
-      const unsigned long long inside = __builtin_amdgcn_ballot_w64(in);
       const int k = stop ? __builtin_ctzll(stop) : 64;
-      const bool ends = k < 64 && ((inside >> k) & 1ull);
+      const bool ends = k < 64 && k <= lim;
       const int steps = k + (ends ? 1 : 0);
       push(vert ? ALN_CIGAR_I : ALN_CIGAR_D, (uint32_t)steps);
       if (vert)

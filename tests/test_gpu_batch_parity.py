@@ -11,12 +11,25 @@ pytestmark = pytest.mark.gpu
 
 PROT = synth.protein_sigma(np.random.default_rng(11))
 
+
+def _mid_sigma(rng):
+    """A symmetric 8-letter table (diagonal +3..+6, off-diagonal -4..+1): alphabets of 5..12 letters take the
+    16-bit kernel's 8-row strips."""
+    t = np.triu(rng.integers(-4, 2, (8, 8)), 1)
+    t = t + t.T
+    np.fill_diagonal(t, rng.integers(3, 7, 8))
+    return t.astype(np.int8)
+
+
+MID = _mid_sigma(np.random.default_rng(12))
+
 SCHEMES = {
     # name: (alphabet, match, mismatch, subst, gap_open, gap_extend)
     "dna_linear": (4, 2, -1, None, 0, -1),
     "dna_affine": (4, 1, -4, None, -5, -2),
     "prot_affine": (20, None, None, PROT, -11, -1),
     "prot_linear": (20, None, None, PROT, 0, -4),
+    "mid8_affine": (8, None, None, MID, -6, -1),
 }
 
 
