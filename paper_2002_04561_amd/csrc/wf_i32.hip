@@ -1359,10 +1359,16 @@ __device__ void walk_wave(const uint16_t* __restrict__ codes, int m, int i, int 
     ++runs;
   }
   if (runs <= cap) {
-    for (int64_t a = 0, b = runs - 1; a < b; ++a, --b) {
-      const uint32_t t = cig[a];
-      cig[a] = cig[b];
-      cig[b] = t;
+    // The runs were stored last to first; reverse them with the whole wave.  Lane l swaps the pairs
+    // (a, runs-1-a) with a = l, l+64, ...: no two lanes touch the same run, and each lane's loads
+    // are its own earlier stores' addresses only through the walk above, which has completed.
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    const int64_t half = runs / 2;
+    for (int64_t a = lane; a < half; a += 64) {
+      const int64_t b = runs - 1 - a;
+      const uint32_t x = cig[a], y = cig[b];
+      cig[a] = y;
+      cig[b] = x;
     }
   }
   *q_begin = i;
