@@ -198,3 +198,49 @@ def test_long_traceback_full_262144(gpu):
     assert clen == len(runs) > 0 and 0 <= qb < qe and 0 <= sb < se
     total, i, j = rescore(1, w.sigma_table(), -3, -1, a, b, qb, sb, runs)
     assert (total, i, j) == (score, qe, se)
+
+
+@pytest.mark.parametrize("seed", range(16))
+def test_long_random_scheme(gpu, seed):
+    """One pair per call under a randomly drawn scheme: 2 to 24 letters, a symmetric or asymmetric table or
+    match/mismatch, linear or affine gaps, any mode, score-only or with the CIGAR, lengths 1..2600 (often a
+    mutated copy with long indels).  Score and end cell, and with a CIGAR the begin cell and every run, must
+    equal the oracle."""
+    rng = np.random.default_rng(9500 + seed)
+    A = int(rng.choice([2, 3, 4, 5, 8, 13, 20, 24]))
+    mode = int(rng.integers(0, 3))
+    sub = match = mismatch = None
+    if rng.random() < 0.6:
+        t = rng.integers(-6, 3, (A, A))
+        if rng.random() < 0.5:
+            t = np.triu(t, 1)
+            t = t + t.T
+        np.fill_diagonal(t, rng.integers(1, 9, A))
+        sub = t.astype(np.int8)
+    else:
+        match, mismatch = int(rng.integers(1, 6)), -int(rng.integers(1, 6))
+    ge = -int(rng.integers(1, 4))
+    go = 0 if rng.random() < 0.3 else -int(rng.integers(1, 12))
+    sc = (oracle.Scoring.matrix(mode, sub.astype(np.int32), go, ge) if sub is not None else
+          oracle.Scoring.simple(mode, A, match, mismatch, go, ge))
+    n, m = int(rng.integers(1, 2600)), int(rng.integers(1, 2600))
+    q = rng.integers(0, A, n, dtype=np.uint8)
+    if rng.random() < 0.7:
+        s = synth.mutate_geometric(rng, q, 0.08, 0.02, 6.0, A)[:m]
+        if len(s) < m:
+            s = np.concatenate([s, rng.integers(0, A, m - len(s), dtype=np.uint8)])
+    else:
+        s = rng.integers(0, A, m, dtype=np.uint8)
+    tb = bool(rng.random() < 0.6)
+    label = "seed %d: A=%d mode=%d go=%d ge=%d table=%s n=%d m=%d tb=%s" % (
+        seed, A, mode, go, ge, sub is not None, n, m, tb)
+    print(label, flush=True)
+    if tb:
+        got = _run_tb(q, s, mode, A, go, ge, match=match, mismatch=mismatch, subst=sub)
+        r = oracle.align(sc, q, s, traceback=True)
+        assert got[:6] == (r.score, r.q_begin, r.q_end, r.s_begin, r.s_end, r.cigar), label
+        assert got[6] == 0, label
+    else:
+        got = _run(q, s, mode, A, go, ge, match=match, mismatch=mismatch, subst=sub)
+        r = oracle.align(sc, q, s, impl="linspace")
+        assert got == (r.score, r.q_end, r.s_end, 0), label
