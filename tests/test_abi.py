@@ -79,3 +79,18 @@ def test_batch_config_validation_on_host():
     st = aln.lib().aln_align_batch_ex(ctypes.byref(sc), 0, None, None, None, None, 0, 0, 0, 0, 0, ctypes.byref(c),
                                       None, None, None, None, 0, None)
     assert st == -1
+
+
+def test_long_size_query_host_checks():
+    """aln_long_workspace_size refuses, before any device query, a traceback whose 4-bit codes would exceed
+    64 GiB (ALN_E_UNSUPPORTED), a score range beyond exact 32-bit lanes (ALN_E_SCORING), an invalid mode
+    and a negative length (ALN_E_INVALID)."""
+    cases = [(aln.Scoring(1, 4, -3, -1, 2, -3), 400000, 400000, aln.TRACEBACK, -6),
+             (aln.Scoring(1, 4, -3, -1, 100, -3), 3000000, 3000000, 0, -3),
+             (aln.Scoring(5, 4, -3, -1, 2, -3), 10, 10, 0, -1),
+             (aln.Scoring(1, 4, -3, -1, 2, -3), -1, 10, 0, -1)]
+    for sc, n, m, flags, e in cases:
+        c = sc.c()
+        out = ctypes.c_size_t(0)
+        st = aln.lib().aln_long_workspace_size(ctypes.byref(c), n, m, flags, ctypes.byref(out))
+        assert st == e, (n, m, flags, st)
