@@ -275,8 +275,9 @@ def run_serve(args):
     torch.cuda.set_device(0)
     warm, _ = serve_stream(64, 1e6, seed=99, long_len=4096)
     AlignServer(sc, budget_bytes=args.budget_gb << 30).run(warm, realtime=False)
+    long_cfg = aln.BatchConfig(wf_waves_per_cu=args.serve_long_waves) if args.serve_long_waves else None
     srv = AlignServer(sc, budget_bytes=args.budget_gb << 30, streams=args.serve_streams, max_pairs=8192,
-                      class_max_pairs={"long": args.serve_long_batch})
+                      class_max_pairs={"long": args.serve_long_batch}, class_configs={"long": long_cfg})
     t_gen = time.perf_counter()
     st = srv.run(reqs, realtime=True)
     print("[bench] served %d requests in %.1f s" % (st["requests"], time.perf_counter() - t_gen), file=sys.stderr)
@@ -287,7 +288,8 @@ def run_serve(args):
         "vs_baseline": None, "dtype": "int16+int32", "data": "synthetic (seeded generator)",
         "config": {"workload": "serve", "requests": len(reqs), "rate_per_s": args.rate, "cells": st["cells"],
                    "budget_bytes": st["budget_bytes"], "peak_bytes": st["peak_bytes"],
-                   "streams": args.serve_streams, "long_batch": args.serve_long_batch},
+                   "streams": args.serve_streams, "long_batch": args.serve_long_batch,
+                   "long_waves_per_cu": args.serve_long_waves},
         "latency_ms": st["classes"], "int32_redo_requests": st["int32_redo"],
     }
     print(json.dumps(out), flush=True)
@@ -304,6 +306,8 @@ def main():
     ap.add_argument("--budget-gb", type=int, default=64, help="serve: device memory budget (GiB)")
     ap.add_argument("--serve-streams", type=int, default=4, help="serve: batches in flight (one HIP stream each)")
     ap.add_argument("--serve-long-batch", type=int, default=8, help="serve: most 65536^2 pairs in one batch call")
+    ap.add_argument("--serve-long-waves", type=int, default=0,
+                    help="serve: wf_waves_per_cu for the 65536^2 pairs' calls (0 = the library's default)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain 1 GiB device-to-device copy (scale for rocprofv3 FETCH_SIZE/WRITE_SIZE)")
     ap.add_argument("--pairs", type=int, default=None, help="override the pair count of a batch workload")

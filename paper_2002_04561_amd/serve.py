@@ -119,7 +119,8 @@ class AlignServer:
     """Runs a request stream through aln_align_batch / aln_align_long with continuous batching."""
 
     def __init__(self, scorings: Dict[str, object], budget_bytes: int, streams: int = 3, max_pairs: int = 8192,
-                 device: str = "cuda", class_max_pairs: Optional[Dict[str, int]] = None):
+                 device: str = "cuda", class_max_pairs: Optional[Dict[str, int]] = None,
+                 class_configs: Optional[Dict[str, object]] = None):
         import torch
 
         import paper_2002_04561_amd as aln
@@ -129,6 +130,7 @@ class AlignServer:
         self.streams = [torch.cuda.Stream(device=device) for _ in range(streams)]
         self.max_pairs = max_pairs
         self.class_max_pairs = dict(class_max_pairs or {})
+        self.class_configs = dict(class_configs or {})  # per class: a BatchConfig (execution choices only)
         self.device = device
         self.completed: List[Completed] = []
         self.cells = 0
@@ -170,7 +172,8 @@ class AlignServer:
                     np.cumsum(cap, out=f.cigar_off[1:])
                 ba = aln.BatchAligner(sc, q, dqo, s, dso, int(max(len(x) for x in qs)),
                                       int(max(len(x) for x in ss)), flags, cigar_capacity=cap, device=self.device,
-                                      total_q=int(qo[-1]), total_s=int(so[-1]))
+                                      total_q=int(qo[-1]), total_s=int(so[-1]),
+                                      config=self.class_configs.get(batch[0].klass))
                 ba.run(stream)
                 f.out, f.cigar = ba.out, ba.cigar
                 f.tensors = [hq, hs, q, s, dqo, dso, ba]
