@@ -200,7 +200,7 @@ def test_long_traceback_full_262144(gpu):
     assert (total, i, j) == (score, qe, se)
 
 
-@pytest.mark.parametrize("seed", range(16))
+@pytest.mark.parametrize("seed", range(32))
 def test_long_random_scheme(gpu, seed):
     """One pair per call under a randomly drawn scheme: 2 to 24 letters, a symmetric or asymmetric table or
     match/mismatch, linear or affine gaps, any mode, score-only or with the CIGAR, lengths 1..2600 (often a

@@ -46,7 +46,7 @@ def _case(seed):
     return w, tb, cfg, label
 
 
-@pytest.mark.parametrize("seed", range(24))
+@pytest.mark.parametrize("seed", range(64))
 def test_random_scheme_batch(gpu, seed):
     import paper_2002_04561_amd as aln
     w, tb, cfg, label = _case(seed)
