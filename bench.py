@@ -277,7 +277,8 @@ def run_serve(args):
     AlignServer(sc, budget_bytes=args.budget_gb << 30).run(warm, realtime=False)
     long_cfg = aln.BatchConfig(wf_waves_per_cu=args.serve_long_waves) if args.serve_long_waves else None
     srv = AlignServer(sc, budget_bytes=args.budget_gb << 30, streams=args.serve_streams, max_pairs=8192,
-                      class_max_pairs={"long": args.serve_long_batch}, class_configs={"long": long_cfg})
+                      class_max_pairs={"long": args.serve_long_batch}, class_configs={"long": long_cfg},
+                      class_max_streams={"long": args.serve_long_streams} if args.serve_long_streams else None)
     t_gen = time.perf_counter()
     st = srv.run(reqs, realtime=True)
     print("[bench] served %d requests in %.1f s" % (st["requests"], time.perf_counter() - t_gen), file=sys.stderr)
@@ -289,7 +290,7 @@ def run_serve(args):
         "config": {"workload": "serve", "requests": len(reqs), "rate_per_s": args.rate, "cells": st["cells"],
                    "budget_bytes": st["budget_bytes"], "peak_bytes": st["peak_bytes"],
                    "streams": args.serve_streams, "long_batch": args.serve_long_batch,
-                   "long_waves_per_cu": args.serve_long_waves},
+                   "long_waves_per_cu": args.serve_long_waves, "long_streams": args.serve_long_streams},
         "latency_ms": st["classes"], "int32_redo_requests": st["int32_redo"],
     }
     print(json.dumps(out), flush=True)
@@ -306,6 +307,8 @@ def main():
     ap.add_argument("--budget-gb", type=int, default=64, help="serve: device memory budget (GiB)")
     ap.add_argument("--serve-streams", type=int, default=4, help="serve: batches in flight (one HIP stream each)")
     ap.add_argument("--serve-long-batch", type=int, default=8, help="serve: most 65536^2 pairs in one batch call")
+    ap.add_argument("--serve-long-streams", type=int, default=0,
+                    help="serve: most 65536^2-pair batches in flight at once (0 = no limit)")
     ap.add_argument("--serve-long-waves", type=int, default=0,
                     help="serve: wf_waves_per_cu for the 65536^2 pairs' calls (0 = the library's default)")
     ap.add_argument("--copy-calibration", action="store_true",

@@ -60,9 +60,11 @@ class Admission:
             raise ValueError("request %d needs %d bytes, more than the whole budget" % (r.rid, request_bytes(r)))
         self.waiting[r.klass].append(r)
 
-    def oldest_class(self) -> Optional[str]:
+    def oldest_class(self, exclude=()) -> Optional[str]:
         best, t = None, None
         for k, dq in self.waiting.items():
+            if k in exclude:
+                continue
             if dq and (t is None or dq[0].arrival < t):
                 best, t = k, dq[0].arrival
         return best
@@ -120,7 +122,7 @@ class AlignServer:
 
     def __init__(self, scorings: Dict[str, object], budget_bytes: int, streams: int = 3, max_pairs: int = 8192,
                  device: str = "cuda", class_max_pairs: Optional[Dict[str, int]] = None,
-                 class_configs: Optional[Dict[str, object]] = None):
+                 class_configs: Optional[Dict[str, object]] = None, class_max_streams: Optional[Dict[str, int]] = None):
         import torch
 
         import paper_2002_04561_amd as aln
@@ -131,6 +133,7 @@ class AlignServer:
         self.max_pairs = max_pairs
         self.class_max_pairs = dict(class_max_pairs or {})
         self.class_configs = dict(class_configs or {})  # per class: a BatchConfig (execution choices only)
+        self.class_max_streams = dict(class_max_streams or {})  # per class: most batches in flight at once
         self.device = device
         self.completed: List[Completed] = []
         self.cells = 0
@@ -219,7 +222,9 @@ class AlignServer:
             launched = False
             for i in range(len(flights)):
                 if flights[i] is None:
-                    k = self.adm.oldest_class()
+                    busy = collections.Counter(f.batch[0].klass for f in flights if f is not None)
+                    full = {c for c, cap in self.class_max_streams.items() if busy[c] >= cap}
+                    k = self.adm.oldest_class(exclude=full)
                     if k is None:
                         break
                     batch = self.adm.take_batch(k, self.class_max_pairs.get(k, self.max_pairs))
