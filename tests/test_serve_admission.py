@@ -55,3 +55,16 @@ def test_long_requests_run_alone_and_oversize_refused():
     assert len(adm.take_batch("x", 8)) == 1
     with pytest.raises(ValueError):
         Admission(100).arrive(_req(2, "x", 1000, 1000, 0.0, tb=True))
+
+
+def test_oldest_class_skips_excluded_classes():
+    """A class at its in-flight cap is passed over: the oldest waiting request of the other classes goes next,
+    and nothing is chosen when only excluded classes wait."""
+    adm = Admission(1 << 30)
+    adm.arrive(_req(0, "long", 64, 64, 0.0))
+    adm.arrive(_req(1, "read", 10, 12, 0.5))
+    adm.arrive(_req(2, "protein", 30, 20, 0.7))
+    assert adm.oldest_class() == "long"
+    assert adm.oldest_class(exclude={"long"}) == "read"
+    assert adm.oldest_class(exclude={"long", "read"}) == "protein"
+    assert adm.oldest_class(exclude={"long", "read", "protein"}) is None
