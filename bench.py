@@ -276,8 +276,9 @@ def run_serve(args):
     warm, _ = serve_stream(64, 1e6, seed=99, long_len=4096)
     AlignServer(sc, budget_bytes=args.budget_gb << 30).run(warm, realtime=False)
     long_cfg = aln.BatchConfig(wf_waves_per_cu=args.serve_long_waves) if args.serve_long_waves else None
+    prot_cfg = aln.BatchConfig(wf_min_cells=args.serve_protein_min_cells) if args.serve_protein_min_cells else None
     srv = AlignServer(sc, budget_bytes=args.budget_gb << 30, streams=args.serve_streams, max_pairs=8192,
-                      class_max_pairs={"long": args.serve_long_batch}, class_configs={"long": long_cfg},
+                      class_max_pairs={"long": args.serve_long_batch}, class_configs={"long": long_cfg, "protein": prot_cfg},
                       class_max_streams={"long": args.serve_long_streams} if args.serve_long_streams else None)
     t_gen = time.perf_counter()
     st = srv.run(reqs, realtime=True)
@@ -290,7 +291,8 @@ def run_serve(args):
         "config": {"workload": "serve", "requests": len(reqs), "rate_per_s": args.rate, "cells": st["cells"],
                    "budget_bytes": st["budget_bytes"], "peak_bytes": st["peak_bytes"],
                    "streams": args.serve_streams, "long_batch": args.serve_long_batch,
-                   "long_waves_per_cu": args.serve_long_waves, "long_streams": args.serve_long_streams},
+                   "long_waves_per_cu": args.serve_long_waves, "long_streams": args.serve_long_streams,
+                   "protein_min_cells": args.serve_protein_min_cells},
         "latency_ms": st["classes"], "int32_redo_requests": st["int32_redo"],
     }
     print(json.dumps(out), flush=True)
@@ -307,6 +309,8 @@ def main():
     ap.add_argument("--budget-gb", type=int, default=64, help="serve: device memory budget (GiB)")
     ap.add_argument("--serve-streams", type=int, default=4, help="serve: batches in flight (one HIP stream each)")
     ap.add_argument("--serve-long-batch", type=int, default=8, help="serve: most 65536^2 pairs in one batch call")
+    ap.add_argument("--serve-protein-min-cells", type=int, default=1,
+                    help="serve: wf_min_cells of the protein calls (0 = the library's default, 2^16)")
     ap.add_argument("--serve-long-streams", type=int, default=0,
                     help="serve: most 65536^2-pair batches in flight at once (0 = no limit)")
     ap.add_argument("--serve-long-waves", type=int, default=0,
