@@ -136,7 +136,9 @@ aln_status_t aln_align_batch(const aln_scoring_t* scoring, int64_t n_pairs, cons
  * out on the device; an autotuner (paper_2002_04561_amd/tune.py) searches them per workload.  A
  * zero field selects the default.
  *   wf_min_cells     score-only calls: pairs with n*m >= wf_min_cells run on the band wavefront
- *                    engine, the others one pair per lane.  0 => 2^16; negative => no pair.
+ *                    engine, the others one pair per lane.  0 => 2^16 for a batch of at least
+ *                    1024 pairs per compute unit (enough to fill the one-pair-per-lane kernels),
+ *                    else 2^12; negative => no pair.
  *   wf_waves_per_cu  persistent waves per compute unit of the wavefront engine, 1..32; 0 => 16,
  *                    or for grouped bands 4 per estimated 4-band group per compute unit, 4..16
  *                    (waves beyond what a compute unit holds start as others finish).

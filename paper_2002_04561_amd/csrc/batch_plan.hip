@@ -236,7 +236,7 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 BatchCfg resolve_cfg(const aln_batch_config_t* c) {
   BatchCfg r;
-  r.wf_min_cells = (int64_t)1 << 16;
+  r.wf_min_cells = 0;
   r.wf_group = 0;
   r.wf_waves_per_cu = kWfWavesPerCUDefault;
   r.waves_given = false;
@@ -261,7 +261,17 @@ BatchCfg resolve_cfg(const aln_batch_config_t* c) {
 
 aln_status_t plan_split(int64_t n_pairs, int64_t total_q, int64_t total_s, bool route_big, const BatchCfg& cfg,
                         SplitPlan* sp) {
-  sp->big_cells = route_big ? cfg.wf_min_cells : INT64_MAX;
+  const int cus = device_cu_count();
+  int64_t min_cells = cfg.wf_min_cells;
+  if (min_cells == 0) {
+    // The one-pair-per-lane kernels keep 8 waves of 128 pairs (16-bit lanes) on each compute unit.
+    // A batch with fewer pairs leaves waves idle there, and each wave pads its pairs to the largest n
+    // and m among them, so such a batch sends its pairs from 2^12 cells up to the band wavefront,
+    // whose bands spread over every compute unit.
+    const int64_t fill = (int64_t)128 * 8 * (cus > 0 ? cus : 1);
+    min_cells = n_pairs >= fill ? (int64_t)1 << 16 : (int64_t)1 << 12;
+  }
+  sp->big_cells = route_big ? min_cells : INT64_MAX;
   sp->orient = cfg.orient;
   size_t off = 0;
   sp->off_small_idx = off;
@@ -284,7 +294,6 @@ aln_status_t plan_split(int64_t n_pairs, int64_t total_q, int64_t total_s, bool 
   // Groups of bands pay off when the batch has few bands per SIMD: then each compute wave is alone
   // on its SIMD and nothing hides its device-memory waits.  Bands are estimated from the letters
   // (rows along the longer sequence, 256 per band).
-  const int cus = device_cu_count();
   const int64_t est_bands = (total_q + total_s) / (2 * kWfBand);
   sp->grouped = cfg.wf_group == 4 || (cfg.wf_group == 0 && est_bands < (int64_t)16 * (cus > 0 ? cus : 1));
   if (sp->grouped && !cfg.waves_given && cus > 0) {

@@ -169,7 +169,7 @@ struct SplitPlan {
 };
 // Resolved execution choices of a batch call (defaults filled in).
 struct BatchCfg {
-  int64_t wf_min_cells;
+  int64_t wf_min_cells;  // 0: by the batch's size (plan_split)
   int wf_group;  // 0: by the batch's size, 1: bands on their own, 4: groups of 4 bands
   int wf_waves_per_cu;
   bool waves_given;  // wf_waves_per_cu came from the caller

@@ -326,7 +326,9 @@ def test_understated_totals_flag_wavefront_pairs(gpu):
     s, so = synth.pack(ss)
     w = synth.Workload("understated", 1, 4, -3, -1, q, qo, s, so, match=2, mismatch=-3)
     dq, dqo, ds, dso = aln.to_device(w)
-    ba = aln.BatchAligner(aln.scoring_of(w), dq, dqo, ds, dso, 1500, 1400, aln.SCORE_ONLY, total_q=64, total_s=64)
+    # the 60 x 70 pairs (4200 cells) stay one per lane: a threshold of 2^16 cells, given explicitly
+    ba = aln.BatchAligner(aln.scoring_of(w), dq, dqo, ds, dso, 1500, 1400, aln.SCORE_ONLY, total_q=64, total_s=64,
+                          config=aln.BatchConfig(wf_min_cells=1 << 16))
     ba.run()
     torch.cuda.synchronize()
     res = ba.results()
