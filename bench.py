@@ -1,21 +1,24 @@
 #!/usr/bin/env python3
 """Benchmark of the alignment hot path on one MI355X: GCUPS, checked against stored oracle results.
 
-  python bench.py [--steps K] [--warmup W] [--workload NAME] [--no-cpu-baseline]
+  python bench.py [--steps K] [--warmup W] [--workload NAME] [--no-cpu-baseline] [--no-serve]
 
 One step is one call of the library on one batch of synthetic, device-resident input (every pass of
 the path the workload needs: planning, the DP relaxation, optimum selection, 16/32-bit redo, and the
 traceback when the workload asks for CIGARs).  Prints one JSON line.
 
 Workloads (synth/__init__.py has the recipes):
-  long     1 pair 262144 x 262144 DNA, local affine (-3/-1, +2/-3), score + end cell       [default]
-  long_tb  the same pair with its CIGAR (4-bit predecessor codes of all cells held in HBM, ~34 GB)
+  protein  65,536 protein pairs, lengths log-uniform 64..16384, local affine (-11/-1), score-only     [default]
+           The line also carries the same batch as one captured HIP graph, as one call per length bin,
+           and one pair per call (the "plain" form), and, unless --no-serve, a "serve" record: the
+           request stream below at 20,000 requests/s with p50/p99 latency per class.
   reads    1,048,576 read/window pairs, semi-global affine (-5/-2, +1/-4), CIGAR for every pair
-  protein  65,536 protein pairs, lengths log-uniform 64..16384, local affine (-11/-1), score-only
+  long     1 pair 262144 x 262144 DNA, local affine (-3/-1, +2/-3), score + end cell
+  long_tb  the same pair with its CIGAR
   nw1k     1 pair 1000 x 1000 DNA, global linear (+2/-1, gap -1), CIGAR
-  serve    a Poisson request stream through the continuous-batching server (paper_2002_04561_amd/serve.py):
-           80% read/window pairs with CIGARs, 19% protein pairs (lengths log-uniform 64..16384), 1% local
-           DNA pairs of 65536 x 65536; reports GCUPS over the run and p50/p99 latency per class
+  serve    only the request stream through the continuous-batching server (paper_2002_04561_amd/serve.py):
+           a Poisson stream of 80% read/window pairs with CIGARs, 19% protein pairs (lengths log-uniform
+           64..16384) and 1% local DNA pairs of 65536 x 65536; GCUPS over the run and p50/p99 latency per class
 """
 import argparse
 import json
@@ -159,6 +162,30 @@ def spot_check(w, res, cigars, idx, expect):
     return "bit-exact vs the stored oracle values of %d pair(s)" % len(expect)
 
 
+DIGESTS = {"reads_semiglobal": "reads_digest.json", "protein_uneven": "protein_digest.json"}
+
+
+def digest_check(w, ba, res):
+    """Every pair of a full batch against the oracle: chunk digests of all results (tests/golden/digest.py)
+    compared with the stored digests of the oracle's results."""
+    path = os.path.join(ROOT, "tests", "golden", DIGESTS.get(w.name, "-"))
+    if not os.path.exists(path):
+        return None
+    g = json.load(open(path))
+    if g["n_pairs"] != w.n_pairs or bool(g["traceback"]) != bool(w.traceback):
+        return None
+    sys.path.insert(0, os.path.join(ROOT, "tests", "golden"))
+    import digest
+    if w.traceback:
+        d = digest.chunk_digests(res, True, ba.cigar.to("cpu").numpy().view(np.uint32), ba.cigar_off.to("cpu").numpy())
+    else:
+        d = digest.chunk_digests(res, False)
+    bad = sum(1 for x, y in zip(d, g["digests"]) if x != y) + abs(len(d) - len(g["digests"]))
+    if bad:
+        return "MISMATCH in %d of %d chunks of all pairs' digests" % (bad, len(g["digests"]))
+    return "all %d pairs bit-exact vs the oracle's digests (%d chunks)" % (w.n_pairs, len(d))
+
+
 def time_graph(ba, stream, steps):
     """The batch call captured once in a HIP graph and replayed `steps` times; ms per replay."""
     import torch
@@ -207,9 +234,9 @@ def time_per_bin(w, flags, stream, steps, config=None):
 
 
 def time_plain(w, flags, stream, count, seed=1):
-    """One pair per call: a random sample of pairs, each aligned by its own aln_align_long call (the
-    single-pair entry point: the pair's rows in bands across the device), each call waiting for the
-    previous; GCUPS = sample cells / summed time."""
+    """One pair per call: a seeded random sample of the batch's pairs, each its own aln_align_batch call with
+    n_pairs = 1 (the same kernels as the batched call, one pair per launch), all enqueued back to back on one
+    stream with one synchronisation at the end; GCUPS = sample cells / elapsed time."""
     import torch
 
     import paper_2002_04561_amd as aln
@@ -217,83 +244,121 @@ def time_plain(w, flags, stream, count, seed=1):
     idx = np.sort(rng.choice(w.n_pairs, size=min(count, w.n_pairs), replace=False))
     n, m = w.lengths()
     sc = aln.scoring_of(w)
+    q, qo, s, so = aln.to_device(w)
+    sizes = [aln.aln_batch_workspace_size(sc, 1, int(n[k]), int(m[k]), int(n[k]), int(m[k]), flags) for k in idx]
+    ws = torch.empty(max(max(sizes), 256), dtype=torch.uint8, device="cuda")
     calls = []
     for k in idx:
-        a, b = w.pair(int(k))
-        calls.append(aln.LongAligner(sc, torch.from_numpy(a.copy()).cuda(), torch.from_numpy(b.copy()).cuda(),
-                                     flags))
-    for ba in calls[:4]:
+        k = int(k)
+        # the pair's offsets are absolute positions in the whole batch's arrays; its lengths bound the totals
+        calls.append(aln.BatchAligner(sc, q, qo[k:k + 2], s, so[k:k + 2], int(n[k]), int(m[k]), flags,
+                                      total_q=int(n[k]), total_s=int(m[k]), workspace=ws))
+    for ba in calls[:8]:
         ba.run(stream)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for ba in calls:
         ba.run(stream)
-        stream.synchronize()
+    torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     cells = float(np.sum(n[idx].astype(np.int64) * m[idx]))
+    res = np.concatenate([ba.results() for ba in calls])
     return {"gcups": round(cells / dt / 1e9, 2), "pairs": len(idx), "cells": cells, "seconds": round(dt, 4),
-            "sample": "%d random pairs, one aln_align_long call per pair, synchronised" % len(idx)}
+            "sample": "%d seeded random pairs, one aln_align_batch call (n_pairs = 1) per pair, enqueued back to "
+                      "back on one stream, one synchronisation" % len(idx)}, idx, res
 
 
-def serve_stream(n_req, rate_hz, seed=5, long_len=65536):
-    """The request mix of the serving workload; arrivals are Poisson at rate_hz."""
+def check_plain(res_plain, idx, res_batched):
+    """The one-pair calls must give the batched call's results."""
+    same = all(np.array_equal(res_plain[f], res_batched[f][idx]) for f in ("score", "q_end", "s_end", "flags"))
+    return "identical to the batched call on all %d pairs" % len(idx) if same else "DIFFERS from the batched call"
+
+
+SERVE_GOLDEN = "serve_sample.json"
+
+
+def serve_requests(n_req, rate_hz, seed=5, long_len=65536):
+    """The serving workload's request stream (synth.serve_stream) as server requests."""
     import synth
     from paper_2002_04561_amd.serve import Request
-    rng = np.random.default_rng(seed)
-    reads = synth.reads_semiglobal(seed=seed, n_pairs=n_req)
-    sig = synth.protein_sigma(rng)
-    reqs, t = [], 0.0
-    for k in range(n_req):
-        t += rng.exponential(1.0 / rate_hz)
-        u = rng.random()
-        if u < 0.8:
-            a, b = reads.pair(k)
-            reqs.append(Request(k, "read", a.copy(), b.copy(), t, traceback=True))
-        elif u < 0.99:
-            n, m = np.rint(np.exp(rng.uniform(np.log(64), np.log(16384), 2))).astype(int)
-            reqs.append(Request(k, "protein", rng.integers(0, 20, n, dtype=np.uint8),
-                                rng.integers(0, 20, m, dtype=np.uint8), t))
-        else:
-            a = rng.integers(0, 4, long_len, dtype=np.uint8)
-            b = synth.mutate_geometric(rng, a, 0.05, 0.01, 3.0)[:long_len]
-            if len(b) < long_len:
-                b = np.concatenate([b, rng.integers(0, 4, long_len - len(b), dtype=np.uint8)])
-            reqs.append(Request(k, "long", a, b, t))  # batched: the bands of all its pairs share one queue
+    items, sig = synth.serve_stream(n_req, rate_hz, seed=seed, long_len=long_len)
+    # the 65536^2 pairs go through batched calls: the bands of all a call's pairs share one queue
+    reqs = [Request(it.rid, it.klass, it.q, it.s, it.arrival, traceback=synth.SERVE_CLASSES[it.klass]["traceback"])
+            for it in items]
     return reqs, sig
 
 
-def run_serve(args):
+def serve_check(srv, n_req, seed):
+    """Compares the served results of the requests whose oracle results tests/golden/ holds (the first
+    requests of each class of the seed-5, 200,000-request stream) bit-exactly."""
+    path = os.path.join(ROOT, "tests", "golden", SERVE_GOLDEN)
+    if not os.path.exists(path) or n_req != 200000 or seed != 5:
+        return "not checked (no stored oracle values for this stream)"
+    g = json.load(open(path))
+    got = {c.rid: c for c in srv.completed}
+    count = 0
+    for klass, rows in g["classes"].items():
+        for e in rows:
+            c = got.get(e["rid"])
+            if c is None:
+                return "MISSING request %d" % e["rid"]
+            score, qb, qe, sb, se, flags = c.result
+            if (score, qe, se, flags) != (e["score"], e["q_end"], e["s_end"], 0):
+                return "MISMATCH request %d (%s)" % (e["rid"], klass)
+            if "cigar" in e and ((qb, sb) != (e["q_begin"], e["s_begin"]) or _cigar_string(c.cigar) != e["cigar"]):
+                return "MISMATCH request %d (%s, CIGAR)" % (e["rid"], klass)
+            count += 1
+    return "bit-exact vs the stored oracle values of %d requests (%s)" % (
+        count, ", ".join("%d %s" % (len(v), k) for k, v in g["classes"].items()))
+
+
+def run_serve(args, log=None):
+    """The request stream through the continuous-batching server; returns the record."""
     import torch
 
     import paper_2002_04561_amd as aln
     import synth
     from paper_2002_04561_amd.serve import AlignServer
-    reqs, sig = serve_stream(args.requests, args.rate)
-    sc = {"read": aln.Scoring(synth.SEMIGLOBAL, 4, -5, -2, match=1, mismatch=-4),
-          "protein": aln.Scoring(synth.LOCAL, 20, -11, -1, subst=sig),
-          "long": aln.Scoring(synth.LOCAL, 4, -3, -1, match=2, mismatch=-3)}
+    t0 = time.perf_counter()
+    reqs, sig = serve_requests(args.requests, args.rate)
+    if log:
+        log("serve: %d requests generated in %.1f s" % (len(reqs), time.perf_counter() - t0))
+    sc = {k: aln.Scoring(c["mode"], c["alphabet_size"], c["gap_open"], c["gap_extend"], match=c.get("match", 0),
+                         mismatch=c.get("mismatch", 0), subst=sig if k == "protein" else None)
+          for k, c in synth.SERVE_CLASSES.items()}
     torch.cuda.set_device(0)
-    warm, _ = serve_stream(64, 1e6, seed=99, long_len=4096)
+    warm, _ = serve_requests(64, 1e6, seed=99, long_len=4096)
     AlignServer(sc, budget_bytes=args.budget_gb << 30).run(warm, realtime=False)
     long_cfg = aln.BatchConfig(wf_waves_per_cu=args.serve_long_waves) if args.serve_long_waves else None
     prot_cfg = aln.BatchConfig(wf_min_cells=args.serve_protein_min_cells) if args.serve_protein_min_cells else None
     srv = AlignServer(sc, budget_bytes=args.budget_gb << 30, streams=args.serve_streams, max_pairs=8192,
                       class_max_pairs={"long": args.serve_long_batch}, class_configs={"long": long_cfg, "protein": prot_cfg},
                       class_max_streams={"long": args.serve_long_streams} if args.serve_long_streams else None)
-    t_gen = time.perf_counter()
+    t_run = time.perf_counter()
     st = srv.run(reqs, realtime=True)
-    print("[bench] served %d requests in %.1f s" % (st["requests"], time.perf_counter() - t_gen), file=sys.stderr)
+    if log:
+        log("serve: %d requests in %.1f s" % (st["requests"], time.perf_counter() - t_run))
+    check = serve_check(srv, args.requests, 5)
+    if log:
+        log("serve parity:", check)
+    return {"gcups": round(st["gcups"], 2), "wall_s": round(st["wall_s"], 3), "requests": len(reqs),
+            "rate_per_s": args.rate, "cells": st["cells"], "latency_ms": st["classes"],
+            "int32_redo_requests": st["int32_redo"], "parity": check, "budget_bytes": st["budget_bytes"],
+            "peak_bytes": st["peak_bytes"], "streams": args.serve_streams, "long_batch": args.serve_long_batch,
+            "protein_min_cells": args.serve_protein_min_cells,
+            "what": "Poisson stream: 80% read/window pairs with CIGARs, 19% protein pairs (64..16384), 1% "
+                    "65536 x 65536 local DNA pairs; latency = completion - arrival"}
+
+
+def print_serve_line(args):
+    rec = run_serve(args, lambda *a: print("[bench]", *a, file=sys.stderr, flush=True))
     out = {
         "metric": "GCUPS (batched vs plain, bit-exact) on one MI355X; p50/p99 request latency",
-        "value": round(st["gcups"], 2), "unit": "GCUPS", "n_gpus": 1, "steps": 1, "warmup": 1,
-        "ms_per_step": round(st["wall_s"] * 1e3, 1), "higher_is_better": True, "scaling": "weak",
+        "value": rec["gcups"], "unit": "GCUPS", "n_gpus": 1, "steps": 1, "warmup": 1,
+        "ms_per_step": round(rec["wall_s"] * 1e3, 1), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "int16+int32", "data": "synthetic (seeded generator)",
-        "config": {"workload": "serve", "requests": len(reqs), "rate_per_s": args.rate, "cells": st["cells"],
-                   "budget_bytes": st["budget_bytes"], "peak_bytes": st["peak_bytes"],
-                   "streams": args.serve_streams, "long_batch": args.serve_long_batch,
-                   "long_waves_per_cu": args.serve_long_waves, "long_streams": args.serve_long_streams,
-                   "protein_min_cells": args.serve_protein_min_cells},
-        "latency_ms": st["classes"], "int32_redo_requests": st["int32_redo"],
+        "config": {"workload": "serve", "requests": rec["requests"], "rate_per_s": args.rate},
+        "parity": rec["parity"], "serve": rec,
     }
     print(json.dumps(out), flush=True)
 
@@ -303,9 +368,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="long", choices=["long", "long_tb", "reads", "protein", "nw1k", "serve"])
-    ap.add_argument("--requests", type=int, default=1000, help="serve: number of requests")
-    ap.add_argument("--rate", type=float, default=15.0, help="serve: Poisson arrival rate (requests/s)")
+    ap.add_argument("--workload", default="protein", choices=["long", "long_tb", "reads", "protein", "nw1k", "serve"])
+    ap.add_argument("--no-serve", action="store_true", help="protein: leave out the serving record")
+    ap.add_argument("--plain-pairs", type=int, default=2048, help="pairs timed one per call (the plain form)")
+    ap.add_argument("--requests", type=int, default=200000, help="serve: number of requests")
+    ap.add_argument("--rate", type=float, default=20000.0, help="serve: Poisson arrival rate (requests/s)")
     ap.add_argument("--budget-gb", type=int, default=64, help="serve: device memory budget (GiB)")
     ap.add_argument("--serve-streams", type=int, default=4, help="serve: batches in flight (one HIP stream each)")
     ap.add_argument("--serve-long-batch", type=int, default=8, help="serve: most 65536^2 pairs in one batch call")
@@ -341,7 +408,7 @@ def main():
         print(json.dumps({"copy_bytes_read": 1 << 30, "copy_bytes_written": 1 << 30}))
         return
     if args.workload == "serve":
-        run_serve(args)
+        print_serve_line(args)
         return
 
     import torch
@@ -404,6 +471,10 @@ def main():
     else:
         cigars = ba.cigars(idx) if w.traceback else None
     check = "skipped" if args.no_check else spot_check(w, res, cigars, idx, expect)
+    if not args.no_check and not long_path and not check.startswith("MISMATCH"):
+        dcheck = digest_check(w, ba, res)
+        if dcheck:
+            check = dcheck if dcheck.startswith("MISMATCH") else "%s; %s" % (dcheck, check)
     log("parity:", check)
 
     gap = "linear" if w.gap_open == 0 else "affine"
@@ -416,6 +487,12 @@ def main():
         per_launch_ms = dom[1][1] / max(dom[1][0], 1)
         launches_per_step = dom[1][0] / args.steps
         cells_per_launch = cells / max(launches_per_step, 1e-9)
+        # the step's cells are attributed to the dominant kernel; when other DP kernels also took a share of
+        # them (pairs split between the band wavefront and one pair per lane), their time is added, so that
+        # the rate is never credited with work another kernel did
+        others = sum(v[1] for k, v in prof.items() if k not in ("plan", dom[0]))
+        if others > 0.01 * dom[1][1]:
+            per_launch_ms = (dom[1][1] + others) / max(dom[1][0], 1)
         achieved = opc * cells_per_launch / (per_launch_ms * 1e-3) / 1e12
         roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 2), "unit": "Tops/s",
                 "frac": round(achieved / peak, 4), "traffic": _measured_traffic(dom[0], w.name), "kernel": dom[0],
@@ -442,8 +519,13 @@ def main():
         out["per_length_bin"] = {"ms_per_step": round(bms, 4), "gcups": round(cells / (bms * 1e-3) / 1e9, 2),
                                  "calls": nbins, "what": "one call per bin of log2 max(n, m), back to back"}
         log("per length bin: %.3f ms in %d calls" % (bms, nbins))
-        out["plain"] = time_plain(w, flags, stream, 256 if w.name == "protein_uneven" else 2048)
-        log("plain: %s" % out["plain"])
+        plain, pidx, pres = time_plain(w, flags, stream, args.plain_pairs)
+        plain["parity"] = check_plain(pres, pidx, res)
+        out["plain"] = plain
+        out["batched_vs_plain"] = round(gcups / plain["gcups"], 2)
+        log("plain: %s" % plain)
+    if args.workload == "protein" and not args.no_serve:
+        out["serve"] = run_serve(args, log)
     if not args.no_cpu_baseline:
         log("timing the oracle on a host sample ...")
         out["cpu_baseline"] = run_cpu_baseline(w)

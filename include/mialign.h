@@ -216,6 +216,15 @@ aln_status_t aln_profile_enable(int on);
 aln_status_t aln_profile_reset(void);
 aln_status_t aln_profile_read(aln_profile_entry_t* entries, int32_t max_entries, int32_t* n_entries);
 
+/* Diagnostic aid: how many times a bounded device-side wait polls before it gives up (device-memory
+ * waits of the band wavefront's hand-offs, and LDS waits between the bands of a workgroup).  A wait
+ * that gives up sets ALN_RES_DEVICE_ERROR on the pairs of its launch instead of blocking; every wave
+ * still leaves its kernel.  0 restores a default (2^22 device-memory polls, 2^26 LDS polls, on the
+ * order of a second each).  The limits are process-wide and read when an align call is enqueued; a
+ * small limit makes waits that would have succeeded give up, which is how tests check that every
+ * kernel exits on that path.  Returns ALN_E_INVALID for a negative count. */
+aln_status_t aln_set_wait_limits(int64_t device_polls, int64_t lds_polls);
+
 /* Human-readable text of a status code (static storage). */
 const char* aln_status_string(aln_status_t status);
 

@@ -89,6 +89,7 @@ _SIGNATURES = {
     "aln_profile_enable": (ctypes.c_int32, [ctypes.c_int]),
     "aln_profile_reset": (ctypes.c_int32, []),
     "aln_profile_read": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
+    "aln_set_wait_limits": (ctypes.c_int32, [ctypes.c_int64, ctypes.c_int64]),
     "aln_status_string": (ctypes.c_char_p, [ctypes.c_int32]),
     "aln_version": (ctypes.c_char_p, []),
 }
@@ -239,6 +240,13 @@ def aln_profile_read() -> dict:
     return {arr[k].name.decode(): (int(arr[k].launches), float(arr[k].total_ms)) for k in range(min(n.value, 64))}
 
 
+def aln_set_wait_limits(device_polls: int = 0, lds_polls: int = 0) -> None:
+    """Poll counts of the bounded device-side waits (0 = the library's defaults); a diagnostic aid."""
+    st = lib().aln_set_wait_limits(device_polls, lds_polls)
+    if st != 0:
+        raise AlnError(st, "aln_set_wait_limits")
+
+
 def aln_status_string(status: int) -> str:
     return lib().aln_status_string(status).decode()
 
@@ -262,7 +270,10 @@ class BatchAligner:
     """Owns the device buffers for repeated aln_align_batch calls over one set of device-resident pairs."""
 
     def __init__(self, scoring: Scoring, q, q_off, s, s_off, max_n: int, max_m: int, flags: int = SCORE_ONLY,
-                 cigar_capacity=None, device="cuda", total_q=None, total_s=None, config: Optional[BatchConfig] = None):
+                 cigar_capacity=None, device="cuda", total_q=None, total_s=None, config: Optional[BatchConfig] = None,
+                 workspace=None):
+        """workspace: an optional caller-owned uint8 device tensor of at least the size query's bytes, for
+        callers that run several aligners one after another on one stream and share one workspace."""
         import torch
         self.torch = torch
         self.config = config
@@ -288,7 +299,12 @@ class BatchAligner:
             self.cigar = torch.empty(max(int(coff[-1]), 1), dtype=torch.int32, device=device)
         self.ws_bytes = aln_batch_workspace_size(scoring, self.n_pairs, self.max_n, self.max_m, self.total_q,
                                                  self.total_s, self.flags)
-        self.workspace = torch.empty(max(self.ws_bytes, 256), dtype=torch.uint8, device=device)
+        if workspace is not None:
+            if workspace.numel() < self.ws_bytes:
+                raise ValueError("workspace of %d bytes, %d needed" % (workspace.numel(), self.ws_bytes))
+            self.workspace = workspace
+        else:
+            self.workspace = torch.empty(max(self.ws_bytes, 256), dtype=torch.uint8, device=device)
 
     def run(self, stream=None):
         if self.config is None:

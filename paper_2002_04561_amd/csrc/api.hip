@@ -13,6 +13,10 @@ int device_cu_count() {
   return cus;
 }
 
+// Poll counts of the bounded device-side waits (aln_set_wait_limits); process-wide.
+static int64_t g_spin_dev = kSpinDevDefault;
+static int64_t g_spin_lds = kSpinLdsDefault;
+
 aln_status_t make_params(const aln_scoring_t* sc, KParams* kp) {
   if (!sc || !kp) return ALN_E_INVALID;
   if (sc->mode < ALN_GLOBAL || sc->mode > ALN_SEMIGLOBAL) return ALN_E_INVALID;
@@ -25,6 +29,8 @@ aln_status_t make_params(const aln_scoring_t* sc, KParams* kp) {
   kp->go = sc->gap_open;
   kp->ge = sc->gap_extend;
   kp->goe = sc->gap_open + sc->gap_extend;
+  kp->spin_dev = g_spin_dev;
+  kp->spin_lds = g_spin_lds;
   const int A = sc->alphabet_size;
   int smax = -1000, smin = 1000;
   if (sc->subst) {
@@ -72,7 +78,14 @@ using namespace mialign;
 
 extern "C" {
 
-const char* aln_version(void) { return "mialign 0.1 (gfx950)"; }
+const char* aln_version(void) { return "mialign 0.2 (gfx950)"; }
+
+aln_status_t aln_set_wait_limits(int64_t device_polls, int64_t lds_polls) {
+  if (device_polls < 0 || lds_polls < 0) return ALN_E_INVALID;
+  g_spin_dev = device_polls ? device_polls : kSpinDevDefault;
+  g_spin_lds = lds_polls ? lds_polls : kSpinLdsDefault;
+  return ALN_OK;
+}
 
 const char* aln_status_string(aln_status_t st) {
   switch (st) {

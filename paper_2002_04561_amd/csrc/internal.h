@@ -27,8 +27,13 @@ struct KParams {
   int32_t use_table;
   int32_t sigma_max;
   int32_t sigma_min;
+  int64_t spin_dev;  // polls of device memory a bounded wait makes before giving up
+  int64_t spin_lds;  // polls of LDS a bounded wait makes before giving up
   int8_t sig[kMaxAlphabet * kMaxAlphabet];  // row-major sigma(q, s) over the real alphabet
 };
+
+constexpr int64_t kSpinDevDefault = 1ll << 22;  // ~0.1-0.5 s of polling device memory
+constexpr int64_t kSpinLdsDefault = 1ll << 26;  // ~1-2 s of polling LDS
 
 // Device workspace layout for the batch path.
 struct BatchPlan {

@@ -39,8 +39,6 @@ constexpr int kRing = 256;                            // columns held by one LDS
 constexpr int kBlkGrouped = 32;                       // steps between lane-0 input refills, grouped
 constexpr int kCourierChunk = 32;                     // columns a courier moves between HBM and LDS at once
 constexpr int kWfBlockAlone = 64 * kWfWavesPerBlock;  // bands on their own: no courier
-constexpr long long kSpinLimit = 1ll << 22;           // polls of device memory before giving up
-constexpr long long kLdsSpinLimit = 1ll << 26;        // polls of LDS before giving up
 
 // Where a band's substitution scores sigma(row letter, column letter) - ge come from:
 //   kProfTable  a 32-bit LDS table indexed by both letters (any score range);
@@ -268,7 +266,7 @@ __global__ __launch_bounds__(kWfBlockAlone) void wf_i32_kernel(const KParams P, 
             for (;;) {
               v = __hip_atomic_load(W.flags + (t - 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
               if (v >= need) break;
-              if (++spins > kSpinLimit || __hip_atomic_load(W.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+              if (++spins > P.spin_dev || __hip_atomic_load(W.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
                 v = -1;
                 break;
               }
@@ -519,7 +517,7 @@ __global__ __launch_bounds__(kWfBlock) void wf_i32_group_kernel(const KParams P,
     long long spins = 0;
     while (__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) < v) {
       __builtin_amdgcn_s_sleep(1);
-      if (++spins > kLdsSpinLimit || __hip_atomic_load(&s_err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) {
+      if (++spins > P.spin_lds || __hip_atomic_load(&s_err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) {
         give_up();
         return false;
       }
@@ -603,7 +601,7 @@ __global__ __launch_bounds__(kWfBlock) void wf_i32_group_kernel(const KParams P,
         idle = 0;
       } else {
         __builtin_amdgcn_s_sleep(1);
-        if (++idle > kSpinLimit || __hip_atomic_load(&s_err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) ||
+        if (++idle > P.spin_dev || __hip_atomic_load(&s_err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) ||
             __hip_atomic_load(W.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
           give_up();
           break;

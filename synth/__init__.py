@@ -259,3 +259,59 @@ def random_pairs(seed: int, n_pairs: int, nmin: int, nmax: int, alphabet: int, m
     q, qo = pack(qs)
     s, so = pack(ss)
     return Workload("random_pairs", mode, alphabet, gap_open, gap_extend, q, qo, s, so, match, mismatch, subst)
+
+
+# Scoring schemes of the serving stream's request classes (plain data: mode, alphabet, gaps, scores).
+SERVE_CLASSES = {
+    "read": dict(mode=SEMIGLOBAL, alphabet_size=4, gap_open=-5, gap_extend=-2, match=1, mismatch=-4, traceback=True),
+    "protein": dict(mode=LOCAL, alphabet_size=20, gap_open=-11, gap_extend=-1, traceback=False),
+    "long": dict(mode=LOCAL, alphabet_size=4, gap_open=-3, gap_extend=-1, match=2, mismatch=-3, traceback=False),
+}
+
+
+@dataclass
+class ServeItem:
+    rid: int
+    klass: str
+    q: np.ndarray
+    s: np.ndarray
+    arrival: float  # seconds from the start of the stream
+
+
+def serve_stream(n_req: int, rate_hz: float, seed: int = 5, long_len: int = 65536, protein_max: int = 16384):
+    """A Poisson request stream mixing three classes: 80% read/window pairs (as reads_semiglobal, CIGAR
+    wanted), 19% protein pairs (lengths log-uniform 64..protein_max, unrelated, 20 letters) and 1% long
+    local DNA pairs of long_len x long_len (the second a mutated copy of the first, as long_dna_local).
+    Returns (items, protein substitution table).  The sequences do not depend on rate_hz."""
+    rng = np.random.default_rng(seed)
+    reads = reads_semiglobal(seed=seed, n_pairs=n_req)
+    sig = protein_sigma(rng)
+    items, t = [], 0.0
+    for k in range(n_req):
+        t += rng.exponential(1.0 / rate_hz)
+        u = rng.random()
+        if u < 0.8:
+            a, b = reads.pair(k)
+            items.append(ServeItem(k, "read", a.copy(), b.copy(), t))
+        elif u < 0.99:
+            n, m = np.rint(np.exp(rng.uniform(np.log(64), np.log(protein_max), 2))).astype(int)
+            items.append(ServeItem(k, "protein", rng.integers(0, 20, n, dtype=np.uint8),
+                                   rng.integers(0, 20, m, dtype=np.uint8), t))
+        else:
+            a = rng.integers(0, 4, long_len, dtype=np.uint8)
+            b = mutate_geometric(rng, a, 0.05, 0.01, 3.0)[:long_len]
+            if len(b) < long_len:
+                b = np.concatenate([b, rng.integers(0, 4, long_len - len(b), dtype=np.uint8)])
+            items.append(ServeItem(k, "long", a, b, t))
+    return items, sig
+
+
+def serve_workload(items, klass: str, sig: np.ndarray) -> Workload:
+    """The requests of one class of a serving stream as a batch Workload (for checking results)."""
+    cls = SERVE_CLASSES[klass]
+    sel = [it for it in items if it.klass == klass]
+    q, qo = pack([it.q for it in sel])
+    s, so = pack([it.s for it in sel])
+    return Workload("serve_" + klass, cls["mode"], cls["alphabet_size"], cls["gap_open"], cls["gap_extend"], q, qo,
+                    s, so, match=cls.get("match"), mismatch=cls.get("mismatch"),
+                    subst=sig if klass == "protein" else None, traceback=cls["traceback"])

@@ -70,8 +70,58 @@ def protein_sample():
     return _sample(synth.protein_uneven(n_pairs=65536), False)
 
 
+def _digests(w):
+    """Chunked digests (tests/golden/digest.py) of the oracle's results on every pair of a batch."""
+    sys.path.insert(0, HERE)
+    import digest
+    t0 = time.time()
+    res, cig, coff = oracle.align_batch(_sc(w), w.q, w.q_off, w.s, w.s_off, traceback=w.traceback)
+    secs = time.time() - t0
+    d = digest.chunk_digests(res, w.traceback, cig, coff)
+    return {"workload": w.name, "n_pairs": w.n_pairs, "traceback": bool(w.traceback), "chunk": digest.CHUNK,
+            "fields": list(digest.FIELDS_TB if w.traceback else digest.FIELDS_SCORE), "digests": d,
+            "oracle_seconds": round(secs, 1)}
+
+
+def reads_digest():
+    """Every pair of the 2^20 read/window batch (semi-global affine, canonical CIGARs), as chunk digests."""
+    return _digests(synth.reads_semiglobal(n_pairs=1 << 20))
+
+
+def protein_digest():
+    """Every pair of the 65536-pair protein batch (local affine, score and end cell), as chunk digests."""
+    return _digests(synth.protein_uneven(n_pairs=65536))
+
+
+SERVE_REQUESTS, SERVE_SEED = 200000, 5
+SERVE_SAMPLE = {"read": 32, "protein": 32, "long": 8}
+
+
+def serve_sample():
+    """The oracle's results for the first requests of each class of the serving stream (seed 5, 200,000
+    requests; the sequences do not depend on the arrival rate)."""
+    items, sig = synth.serve_stream(SERVE_REQUESTS, 1.0, seed=SERVE_SEED)
+    out = {"workload": "serve_stream(seed=%d, n_req=%d)" % (SERVE_SEED, SERVE_REQUESTS), "classes": {}}
+    for klass, count in SERVE_SAMPLE.items():
+        sel = [it for it in items if it.klass == klass][:count]
+        w = synth.serve_workload(sel, klass, sig)
+        res, cig, coff = oracle.align_batch(_sc(w), w.q, w.q_off, w.s, w.s_off, traceback=w.traceback)
+        rows = []
+        for k, it in enumerate(sel):
+            e = {"rid": it.rid, "score": int(res["score"][k]), "q_end": int(res["q_end"][k]),
+                 "s_end": int(res["s_end"][k])}
+            if w.traceback:
+                L = int(res["cigar_len"][k])
+                e.update(q_begin=int(res["q_begin"][k]), s_begin=int(res["s_begin"][k]),
+                         cigar=oracle.cigar_string([(int(x) >> 4, int(x) & 15) for x in cig[coff[k]:coff[k] + L]]))
+            rows.append(e)
+        out["classes"][klass] = rows
+    return out
+
+
 JOBS = {"long_local_262144": long_local_262144, "global_1k": global_1k, "reads_sample": reads_sample,
-        "protein_sample": protein_sample}
+        "protein_sample": protein_sample, "reads_digest": reads_digest, "protein_digest": protein_digest,
+        "serve_sample": serve_sample}
 
 if __name__ == "__main__":
     names = sys.argv[1:] or list(JOBS)
@@ -81,4 +131,4 @@ if __name__ == "__main__":
         with open(path, "w") as f:
             json.dump(val, f, indent=1)
             f.write("\n")
-        print("wrote", path, {k: v for k, v in val.items() if k != "cigar"})
+        print("wrote", path, {k: (v if len(str(v)) < 200 else "...") for k, v in val.items() if k != "cigar"})

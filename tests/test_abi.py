@@ -94,3 +94,10 @@ def test_long_size_query_host_checks():
         out = ctypes.c_size_t(0)
         st = aln.lib().aln_long_workspace_size(ctypes.byref(c), n, m, flags, ctypes.byref(out))
         assert st == e, (n, m, flags, st)
+
+
+def test_wait_limits_host_checks():
+    """aln_set_wait_limits refuses negative poll counts; 0 restores the defaults (no device work)."""
+    assert aln.lib().aln_set_wait_limits(-1, 0) == -1
+    assert aln.lib().aln_set_wait_limits(0, -5) == -1
+    assert aln.lib().aln_set_wait_limits(0, 0) == 0

@@ -1,16 +1,21 @@
 """The two benchmark batches at full size, in the launch configurations the benchmark measures:
 2^20 read/window pairs with CIGARs (semi-global affine) and 65,536 protein pairs of uneven lengths
-(local affine, score-only).  A seeded sample of 64 pairs of each is checked bit-exactly against the
-oracle's results stored in tests/golden/ (written by tests/golden/make_golden.py, which calls only the
-oracle); every other pair must come back without an error flag and with its end cell inside its
-matrix."""
+(local affine, score-only).  Every pair is checked bit-exactly against the oracle: the results of all
+pairs, CIGARs included, are hashed in chunks of consecutive pairs (tests/golden/digest.py) and compared
+with the digests of the oracle's results stored in tests/golden/ (written by
+tests/golden/make_golden.py, which calls only the oracle).  A seeded sample of 64 pairs of each is also
+compared field by field, which names the pair when something differs."""
 import json
 import os
+import sys
 
 import numpy as np
 import pytest
 
 import synth
+
+sys.path.insert(0, os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden"))
+import digest  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -40,6 +45,20 @@ def _run(w, flags, config):
     return ba
 
 
+def _check_digests(w, ba, res, name):
+    """Chunk digests of every pair's results against the oracle's stored digests."""
+    g = json.load(open(os.path.join(HERE, "golden", name)))
+    assert g["n_pairs"] == w.n_pairs and g["workload"] == w.name and g["chunk"] == digest.CHUNK
+    if w.traceback:
+        cig = ba.cigar.to("cpu").numpy().view(np.uint32)
+        d = digest.chunk_digests(res, True, cig, ba.cigar_off.to("cpu").numpy())
+    else:
+        d = digest.chunk_digests(res, False)
+    bad = [c for c, (x, y) in enumerate(zip(d, g["digests"])) if x != y]
+    assert len(d) == len(g["digests"]) and not bad, "chunks of %d pairs differing from the oracle: %s" % (
+        digest.CHUNK, bad[:20])
+
+
 def _check_all(w, res):
     n, m = w.lengths()
     import paper_2002_04561_amd as aln
@@ -67,12 +86,16 @@ def test_reads_full_batch(gpu, reads, cfg):
     _check_all(reads, res)
     idx = [int(e["k"]) for e in golden["pairs"]]
     cig = ba.cigars(idx)
+    sample_bad = []
     for e in golden["pairs"]:
         k = int(e["k"])
         g = (int(res["score"][k]), int(res["q_begin"][k]), int(res["q_end"][k]), int(res["s_begin"][k]),
              int(res["s_end"][k]), _cigar_string(cig[k]))
         o = (e["score"], e["q_begin"], e["q_end"], e["s_begin"], e["s_end"], e["cigar"])
-        assert g == o, (cfg, k, g, o)
+        if g != o:
+            sample_bad.append((cfg, k, g, o))
+    assert not sample_bad, sample_bad[:4]
+    _check_digests(reads, ba, res, "reads_digest.json")
 
 
 @pytest.mark.parametrize("cfg", list(PROTEIN_CONFIGS))
@@ -87,3 +110,4 @@ def test_protein_full_batch(gpu, protein, cfg):
         k = int(e["k"])
         g = (int(res["score"][k]), int(res["q_end"][k]), int(res["s_end"][k]))
         assert g == (e["score"], e["q_end"], e["s_end"]), (cfg, k, g)
+    _check_digests(protein, ba, res, "protein_digest.json")

@@ -1,34 +1,40 @@
-"""Serving loop: each request's result is the same alone and in the mix; memory stays within budget."""
+"""Serving loop: every served result equals the oracle's and the same request's result alone;
+memory stays within budget."""
 import numpy as np
 import pytest
 
 import synth
+from helpers import run_oracle
 
 pytestmark = pytest.mark.gpu
 
 
 def _stream(seed, n_req, rate_hz):
+    """The serving mix (synth.serve_stream) at test sizes: proteins up to 2048 letters, long pairs of
+    4096 x 4096 run alone through aln_align_long."""
     from paper_2002_04561_amd.serve import Request
-    rng = np.random.default_rng(seed)
-    reads = synth.reads_semiglobal(seed=seed, n_pairs=n_req)
-    sig = synth.protein_sigma(rng)
-    reqs = []
-    t = 0.0
-    for k in range(n_req):
-        t += rng.exponential(1.0 / rate_hz)
-        u = rng.random()
-        if u < 0.8:
-            a, b = reads.pair(k)
-            reqs.append(Request(k, "read", a.copy(), b.copy(), t, traceback=True))
-        elif u < 0.99:
-            n, m = np.rint(np.exp(rng.uniform(np.log(64), np.log(2048), 2))).astype(int)
-            reqs.append(Request(k, "protein", rng.integers(0, 20, n, dtype=np.uint8),
-                                rng.integers(0, 20, m, dtype=np.uint8), t))
-        else:
-            a = rng.integers(0, 4, 4096, dtype=np.uint8)
-            b = synth.mutate_geometric(rng, a, 0.05, 0.01, 3.0)[:4096]
-            reqs.append(Request(k, "long", a, b, t, long=True))
-    return reqs, sig
+    items, sig = synth.serve_stream(n_req, rate_hz, seed=seed, long_len=4096, protein_max=2048)
+    reqs = [Request(it.rid, it.klass, it.q, it.s, it.arrival, traceback=synth.SERVE_CLASSES[it.klass]["traceback"],
+                    long=it.klass == "long") for it in items]
+    return reqs, items, sig
+
+
+def _oracle_results(items, sig):
+    """rid -> (score, q_begin, q_end, s_begin, s_end, flags) and CIGAR runs (None when score-only), from
+    the oracle, per class."""
+    out = {}
+    for klass in synth.SERVE_CLASSES:
+        sel = [it for it in items if it.klass == klass]
+        if not sel:
+            continue
+        w = synth.serve_workload(sel, klass, sig)
+        res, cig = run_oracle(w, w.traceback)
+        for k, it in enumerate(sel):
+            qb = int(res["q_begin"][k]) if w.traceback else -1
+            sb = int(res["s_begin"][k]) if w.traceback else -1
+            tup = (int(res["score"][k]), qb, int(res["q_end"][k]), sb, int(res["s_end"][k]), int(res["flags"][k]))
+            out[it.rid] = (tup, cig[k] if w.traceback else None)
+    return out
 
 
 def _scorings(sig):
@@ -50,9 +56,9 @@ def _alone(reqs, scorings):
     return out
 
 
-def test_mix_equals_alone_and_budget(gpu):
-    from paper_2002_04561_amd.serve import AlignServer, request_bytes
-    reqs, sig = _stream(21, 400, 20000.0)
+def test_mix_equals_oracle_and_alone_and_budget(gpu):
+    from paper_2002_04561_amd.serve import AlignServer
+    reqs, items, sig = _stream(21, 400, 20000.0)
     sc = _scorings(sig)
     budget = 64 << 20
     srv = AlignServer(sc, budget_bytes=budget, streams=3, max_pairs=64)
@@ -60,17 +66,24 @@ def test_mix_equals_alone_and_budget(gpu):
     assert stats["requests"] == len(reqs)
     assert stats["peak_bytes"] <= budget
     got = {c.rid: (c.result, c.cigar) for c in srv.completed}
+    assert sorted(got) == sorted(r.rid for r in reqs)
+    expect = _oracle_results(items, sig)
+    bad = [(rid, got[rid], expect[rid]) for rid in got if got[rid] != expect[rid]]
+    assert not bad, [str(b)[:300] for b in bad[:5]]
     alone = _alone(reqs, sc)
     bad = [rid for rid in got if got[rid] != alone[rid]]
     assert not bad, bad[:10]
-    assert set(stats["classes"]) == {"read", "protein", "long"} or len(stats["classes"]) >= 2
+    assert set(stats["classes"]) == {"read", "protein", "long"}
 
 
 def test_tiny_budget_completes(gpu):
     from paper_2002_04561_amd.serve import AlignServer, request_bytes
-    reqs, sig = _stream(22, 60, 50000.0)
+    reqs, items, sig = _stream(22, 60, 50000.0)
     reqs = [r for r in reqs if not r.long]
     budget = max(request_bytes(r) for r in reqs) + 1
     srv = AlignServer(_scorings(sig), budget_bytes=budget, streams=2, max_pairs=64)
     stats = srv.run(reqs, realtime=False)
     assert stats["requests"] == len(reqs) and stats["peak_bytes"] <= budget
+    expect = _oracle_results([it for it in items if it.klass != "long"], sig)
+    bad = [c.rid for c in srv.completed if (c.result, c.cigar) != expect[c.rid]]
+    assert not bad, bad[:10]
