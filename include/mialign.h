@@ -90,6 +90,8 @@ typedef struct {
 #define ALN_TRACEBACK 1u   /* aln_align_batch: also write the canonical CIGAR of every pair */
 #define ALN_FORCE_INT32 2u /* skip the packed 16-bit path */
 #define ALN_FORCE_INT16 4u /* test hook: run local pairs in 16 bits even when the a-priori bound fails */
+#define ALN_LINEAR_SPACE 8u /* aln_align_long with ALN_TRACEBACK: trace back in linear space (checkpoints and
+                               tiles relaxed again) even where a code per cell would fit */
 
 /* result flags */
 #define ALN_RES_INT32_REDO 1u  /* the 16-bit pass saturated; the pair was recomputed in 32 bits */
@@ -97,6 +99,8 @@ typedef struct {
 #define ALN_RES_BAD_CODE 4u    /* a sequence code >= alphabet_size; no score computed */
 #define ALN_RES_TOO_LONG 8u    /* n > max_n or m > max_m (the bounds the workspace was sized for) */
 #define ALN_RES_DEVICE_ERROR 16u /* a bounded device-side wait gave up; the result is not valid */
+#define ALN_RES_BAD_END 32u    /* aln_traceback: the given end cell lies outside the pair's matrix, or H there
+                                  differs from the given score; no CIGAR written */
 
 /* CIGAR words: (run_length << 4) | op, op 0 = M (match or mismatch), 1 = I (query letter
  * against a gap), 2 = D (subject letter against a gap), in alignment order. */
@@ -180,6 +184,47 @@ aln_status_t aln_align_batch_ex(const aln_scoring_t* scoring, int64_t n_pairs, c
                                 const aln_batch_config_t* config, aln_result_t* out, uint32_t* cigar,
                                 const int64_t* cigar_off, void* workspace, size_t workspace_bytes,
                                 hipStream_t stream);
+
+/* Bytes of device workspace aln_traceback needs for n_pairs pairs whose lengths are at most max_n and
+ * max_m.  Returns ALN_OK and sets *bytes. */
+aln_status_t aln_traceback_workspace_size(const aln_scoring_t* scoring, int64_t n_pairs, int64_t max_n,
+                                          int64_t max_m, size_t* bytes);
+
+/* Re-emits the canonical alignment of pairs whose optimum a forward call already found (the traceback
+ * of AnySeq Sec. III-A, started from the given end cell; Sec. III-C returns the alignment beside the
+ * score).  Pair k's matrix is relaxed again only up to its end cell (fwd[k].q_end, fwd[k].s_end):
+ * every value there equals that of the whole matrix, so the walk back from that cell is the one
+ * aln_align_batch with ALN_TRACEBACK takes.  Typical use: a batch run score-only, or one whose
+ * CIGAR buffers were too small (ALN_RES_CIGAR_TRUNC, cigar_len = the words needed), is traced back
+ * for the affected pairs only, into resized buffers.
+ *   q, q_off, s, s_off, max_n, max_m   as for aln_align_batch (DEVICE arrays)
+ *   fwd           DEVICE  aln_result_t[n_pairs] from aln_align_batch / aln_align_long: score and end cell
+ *   out           DEVICE  aln_result_t[n_pairs]; may be the same array as fwd.  score, q_end and s_end
+ *                         are fwd's; q_begin, s_begin, cigar_len and flags are set.  A pair whose fwd
+ *                         carries ALN_RES_BAD_CODE, ALN_RES_TOO_LONG or ALN_RES_DEVICE_ERROR keeps
+ *                         that flag and gets no CIGAR; ALN_RES_BAD_END is set when the end cell lies
+ *                         outside the matrix or H there is not fwd's score.
+ *   cigar, cigar_off  DEVICE  as for aln_align_batch; ALN_RES_CIGAR_TRUNC when a pair's room is short
+ *   workspace     DEVICE  at least aln_traceback_workspace_size(...) bytes, 256-byte aligned
+ * Pairs run one per lane in 32-bit lanes, in the order given. */
+aln_status_t aln_traceback(const aln_scoring_t* scoring, int64_t n_pairs, const uint8_t* q, const int64_t* q_off,
+                           const uint8_t* s, const int64_t* s_off, int64_t max_n, int64_t max_m,
+                           const aln_result_t* fwd, aln_result_t* out, uint32_t* cigar, const int64_t* cigar_off,
+                           void* workspace, size_t workspace_bytes, hipStream_t stream);
+
+/* Renders an alignment as the two gapped strings of AnySeq's C interface (Sec. III-C): q_aln and
+ * s_aln receive the aligned parts of the query and the subject, letters mapped through `letters`
+ * (letter k is letters[k]; codes outside it render as '?') and '-' where the other sequence has a
+ * letter against a gap.  HOST only; no device work.
+ *   q, s            HOST  the pair's codes (the whole sequences)
+ *   result          HOST  the pair's result (q_begin, s_begin and cigar_len are used)
+ *   cigar           HOST  result->cigar_len CIGAR words
+ *   q_aln, s_aln    HOST  buffers of `capacity` chars each; both are NUL-terminated
+ * Returns ALN_OK, or ALN_E_INVALID if a pointer is NULL, the CIGAR runs past the sequences, or the
+ * alignment (length + 1) does not fit in capacity. */
+aln_status_t aln_cigar_to_gapped(const uint8_t* q, int64_t n, const uint8_t* s, int64_t m,
+                                 const aln_result_t* result, const uint32_t* cigar, const char* letters,
+                                 char* q_aln, char* s_aln, int64_t capacity);
 
 /* Bytes of device workspace aln_align_long needs for an n x m problem and the given flags. */
 aln_status_t aln_long_workspace_size(const aln_scoring_t* scoring, int64_t n, int64_t m, uint32_t flags,

@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libmialign.so")
 
 GLOBAL, LOCAL, SEMIGLOBAL = 0, 1, 2
 SCORE_ONLY, TRACEBACK, FORCE_INT32, FORCE_INT16 = 0, 1, 2, 4
-RES_INT32_REDO, RES_CIGAR_TRUNC, RES_BAD_CODE, RES_TOO_LONG, RES_DEVICE_ERROR = 1, 2, 4, 8, 16
+RES_INT32_REDO, RES_CIGAR_TRUNC, RES_BAD_CODE, RES_TOO_LONG, RES_DEVICE_ERROR, RES_BAD_END = 1, 2, 4, 8, 16, 32
 CIGAR_M, CIGAR_I, CIGAR_D = 0, 1, 2
 
 STATUS = {0: "ALN_OK", -1: "ALN_E_INVALID", -2: "ALN_E_ALPHABET", -3: "ALN_E_SCORING", -4: "ALN_E_WORKSPACE",
@@ -90,6 +90,15 @@ _SIGNATURES = {
     "aln_profile_reset": (ctypes.c_int32, []),
     "aln_profile_read": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
     "aln_set_wait_limits": (ctypes.c_int32, [ctypes.c_int64, ctypes.c_int64]),
+    "aln_traceback_workspace_size": (ctypes.c_int32, [ctypes.POINTER(aln_scoring_t), ctypes.c_int64, ctypes.c_int64,
+                                                      ctypes.c_int64, ctypes.POINTER(ctypes.c_size_t)]),
+    "aln_traceback": (ctypes.c_int32, [ctypes.POINTER(aln_scoring_t), ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64,
+                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                       ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
+    "aln_cigar_to_gapped": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64,
+                                             ctypes.c_void_p, ctypes.c_void_p, ctypes.c_char_p, ctypes.c_void_p,
+                                             ctypes.c_void_p, ctypes.c_int64]),
     "aln_status_string": (ctypes.c_char_p, [ctypes.c_int32]),
     "aln_version": (ctypes.c_char_p, []),
 }
@@ -238,6 +247,78 @@ def aln_profile_read() -> dict:
     if st != 0:
         raise AlnError(st, "aln_profile_read")
     return {arr[k].name.decode(): (int(arr[k].launches), float(arr[k].total_ms)) for k in range(min(n.value, 64))}
+
+
+def aln_traceback_workspace_size(scoring: Scoring, n_pairs: int, max_n: int, max_m: int) -> int:
+    out = ctypes.c_size_t(0)
+    sc = scoring.c()
+    st = lib().aln_traceback_workspace_size(ctypes.byref(sc), n_pairs, max_n, max_m, ctypes.byref(out))
+    if st != 0:
+        raise AlnError(st, "aln_traceback_workspace_size")
+    return int(out.value)
+
+
+def aln_traceback(scoring: Scoring, n_pairs: int, q, q_off, s, s_off, max_n: int, max_m: int, fwd, out, cigar,
+                  cigar_off, workspace, workspace_bytes: int, stream=None) -> int:
+    """Same arguments as the C function; tensors are torch device tensors.  Returns the status code."""
+    sc = scoring.c()
+    return int(lib().aln_traceback(ctypes.byref(sc), n_pairs, _ptr(q), _ptr(q_off), _ptr(s), _ptr(s_off), max_n, max_m,
+                                   _ptr(fwd), _ptr(out), _ptr(cigar), _ptr(cigar_off), _ptr(workspace),
+                                   workspace_bytes, _stream_handle(stream)))
+
+
+def traceback_pairs(scoring: Scoring, q, q_off, s, s_off, max_n: int, max_m: int, fwd, cigar_capacity=None,
+                    device="cuda", stream=None):
+    """aln_traceback over device-resident pairs and their forward results (an int32 tensor holding
+    aln_result_t records).  Returns (results structured array, CIGAR run lists), after synchronising."""
+    import torch
+    n_pairs = int(q_off.numel()) - 1
+    if cigar_capacity is None:
+        qo = q_off.to("cpu").numpy()
+        so = s_off.to("cpu").numpy()
+        cap = np.maximum((qo[1:] - qo[:-1]) + (so[1:] - so[:-1]), 1)
+    else:
+        cap = np.asarray(cigar_capacity, dtype=np.int64)
+    coff = np.zeros(n_pairs + 1, dtype=np.int64)
+    np.cumsum(cap, out=coff[1:])
+    cig = torch.empty(max(int(coff[-1]), 1), dtype=torch.int32, device=device)
+    dcoff = torch.from_numpy(coff).to(device)
+    out = torch.empty(n_pairs * 8, dtype=torch.int32, device=device)
+    nbytes = aln_traceback_workspace_size(scoring, n_pairs, max_n, max_m)
+    ws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
+    st = aln_traceback(scoring, n_pairs, q, q_off, s, s_off, max_n, max_m, fwd, out, cig, dcoff, ws, nbytes, stream)
+    if st != 0:
+        raise AlnError(st, "aln_traceback")
+    torch.cuda.synchronize()
+    res = out.to("cpu").numpy().view(RESULT_DTYPE)
+    words = cig.to("cpu").numpy().view(np.uint32)
+    runs = []
+    for k in range(n_pairs):
+        L = min(int(res["cigar_len"][k]), int(coff[k + 1] - coff[k]))
+        runs.append([(int(x) >> 4, int(x) & 15) for x in words[coff[k]:coff[k] + L]])
+    return res, runs
+
+
+def aln_cigar_to_gapped(q: np.ndarray, s: np.ndarray, result, runs, letters: Optional[str] = None):
+    """The alignment as two gapped strings (host only).  result: one RESULT_DTYPE record (or a tuple-like
+    with q_begin, s_begin); runs: [(length, op), ...].  Returns (q_aln, s_aln)."""
+    qa = np.ascontiguousarray(q, dtype=np.uint8)
+    sa = np.ascontiguousarray(s, dtype=np.uint8)
+    words = np.array([(int(L) << 4) | int(op) for L, op in runs], dtype=np.uint32)
+    rec = np.zeros(1, dtype=RESULT_DTYPE)
+    rec["q_begin"] = int(result["q_begin"])
+    rec["s_begin"] = int(result["s_begin"])
+    rec["cigar_len"] = len(words)
+    cap = int(sum(int(L) for L, _ in runs)) + 1
+    qbuf = ctypes.create_string_buffer(cap)
+    sbuf = ctypes.create_string_buffer(cap)
+    st = lib().aln_cigar_to_gapped(qa.ctypes.data if len(qa) else None, len(qa), sa.ctypes.data if len(sa) else None,
+                                   len(sa), rec.ctypes.data, words.ctypes.data if len(words) else None,
+                                   letters.encode() if letters is not None else None, ctypes.addressof(qbuf),
+                                   ctypes.addressof(sbuf), cap)
+    if st != 0:
+        raise AlnError(st, "aln_cigar_to_gapped")
+    return qbuf.value.decode(), sbuf.value.decode()
 
 
 def aln_set_wait_limits(device_polls: int = 0, lds_polls: int = 0) -> None:

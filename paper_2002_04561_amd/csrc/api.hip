@@ -253,19 +253,108 @@ aln_status_t aln_align_batch_ex(const aln_scoring_t* scoring, int64_t n_pairs, c
                           ALN_RES_INT32_REDO, ticket32, stream);
 }
 
-// Traceback of one long pair stores 4 bits per cell; beyond this the call is refused.
+// aln_traceback: the 32-bit one-pair-per-lane slabs, then the group ticket.
+static aln_status_t tb_layout(const KParams& kp, int64_t n_pairs, int64_t max_n, int64_t max_m, BatchPlan* bp,
+                              size_t* off_ticket, size_t* total) {
+  aln_status_t st = plan_batch_i32(kp, n_pairs, max_n, max_m, true, bp);
+  if (st != ALN_OK) return st;
+  *off_ticket = (bp->total_bytes + 255) & ~(size_t)255;
+  *total = *off_ticket + 256;
+  return ALN_OK;
+}
+
+aln_status_t aln_traceback_workspace_size(const aln_scoring_t* scoring, int64_t n_pairs, int64_t max_n,
+                                          int64_t max_m, size_t* bytes) {
+  if (!bytes || n_pairs < 0 || max_n < 0 || max_m < 0) return ALN_E_INVALID;
+  KParams kp;
+  aln_status_t st = make_params(scoring, &kp);
+  if (st != ALN_OK) return st;
+  if (!fits_i32(kp, max_n, max_m)) return ALN_E_SCORING;
+  BatchPlan bp;
+  size_t off_ticket = 0;
+  st = tb_layout(kp, n_pairs, max_n, max_m, &bp, &off_ticket, bytes);
+  return st;
+}
+
+aln_status_t aln_traceback(const aln_scoring_t* scoring, int64_t n_pairs, const uint8_t* q, const int64_t* q_off,
+                           const uint8_t* s, const int64_t* s_off, int64_t max_n, int64_t max_m,
+                           const aln_result_t* fwd, aln_result_t* out, uint32_t* cigar, const int64_t* cigar_off,
+                           void* workspace, size_t workspace_bytes, hipStream_t stream) {
+  if (n_pairs < 0 || max_n < 0 || max_m < 0) return ALN_E_INVALID;
+  KParams kp;
+  aln_status_t st = make_params(scoring, &kp);
+  if (st != ALN_OK) return st;
+  if (n_pairs == 0) return ALN_OK;
+  if (!q_off || !s_off || !fwd || !out || !cigar || !cigar_off) return ALN_E_INVALID;
+  if ((!q && max_n > 0) || (!s && max_m > 0)) return ALN_E_INVALID;
+  if (n_pairs >= (1ll << 31)) return ALN_E_INVALID;
+  if (!fits_i32(kp, max_n, max_m)) return ALN_E_SCORING;
+  BatchPlan bp;
+  size_t off_ticket = 0, total = 0;
+  st = tb_layout(kp, n_pairs, max_n, max_m, &bp, &off_ticket, &total);
+  if (st != ALN_OK) return st;
+  if (!workspace || workspace_bytes < total) return ALN_E_WORKSPACE;
+  int* ticket = reinterpret_cast<int*>(static_cast<char*>(workspace) + off_ticket);
+  hipLaunchKernelGGL(fill_i32_kernel, dim3(1), dim3(64), 0, stream, ticket, 1, 0);
+  return launch_batch_i32(kp, bp, q, q_off, s, s_off, true, out, cigar, cigar_off, workspace, nullptr, nullptr, 0u,
+                          ticket, stream, fwd);
+}
+
+aln_status_t aln_cigar_to_gapped(const uint8_t* q, int64_t n, const uint8_t* s, int64_t m,
+                                 const aln_result_t* result, const uint32_t* cigar, const char* letters,
+                                 char* q_aln, char* s_aln, int64_t capacity) {
+  if ((!q && n > 0) || (!s && m > 0) || !result || !q_aln || !s_aln || capacity < 1 || n < 0 || m < 0)
+    return ALN_E_INVALID;
+  if (result->cigar_len < 0 || (result->cigar_len > 0 && !cigar)) return ALN_E_INVALID;
+  int64_t i = result->q_begin, j = result->s_begin, len = 0;
+  if (i < 0 || j < 0 || i > n || j > m) return ALN_E_INVALID;
+  const int64_t nl = letters ? (int64_t)std::strlen(letters) : 26;
+  auto letter = [&](uint8_t c) -> char {
+    if (c >= nl) return '?';
+    return letters ? letters[c] : (char)('A' + c);
+  };
+  for (int32_t k = 0; k < result->cigar_len; ++k) {
+    const uint32_t op = cigar[k] & 15u, run = cigar[k] >> 4;
+    if (op > ALN_CIGAR_D) return ALN_E_INVALID;
+    if (len + (int64_t)run + 1 > capacity) return ALN_E_INVALID;
+    if ((op != ALN_CIGAR_D && i + run > n) || (op != ALN_CIGAR_I && j + run > m)) return ALN_E_INVALID;
+    for (uint32_t r = 0; r < run; ++r, ++len) {
+      q_aln[len] = op == ALN_CIGAR_D ? '-' : letter(q[i++]);
+      s_aln[len] = op == ALN_CIGAR_I ? '-' : letter(s[j++]);
+    }
+  }
+  q_aln[len] = 0;
+  s_aln[len] = 0;
+  return ALN_OK;
+}
+
+// Traceback of one long pair stores 4 bits per cell while that fits under this; above it (or with
+// ALN_LINEAR_SPACE) the pair is traced back in linear space from checkpoints.
 static const int64_t kMaxLongCodeBytes = (int64_t)64 << 30;
+
+static bool long_linear_space(int64_t n, int64_t m, uint32_t flags) {
+  if (!(flags & ALN_TRACEBACK)) return false;
+  return (flags & ALN_LINEAR_SPACE) || (n + kWfBand) / 2 * m > kMaxLongCodeBytes;
+}
+
+static const uint32_t kLongFlags = ALN_TRACEBACK | ALN_FORCE_INT32 | ALN_FORCE_INT16 | ALN_LINEAR_SPACE;
 
 aln_status_t aln_long_workspace_size(const aln_scoring_t* scoring, int64_t n, int64_t m, uint32_t flags,
                                      size_t* bytes) {
   if (!bytes || n < 0 || m < 0 || n >= (1ll << 31) || m >= (1ll << 31)) return ALN_E_INVALID;
-  if (flags & ~(ALN_TRACEBACK | ALN_FORCE_INT32 | ALN_FORCE_INT16)) return ALN_E_INVALID;
+  if (flags & ~kLongFlags) return ALN_E_INVALID;
   const bool tb = (flags & ALN_TRACEBACK) != 0;
-  if (tb && (n + kWfBand) / 2 * m > kMaxLongCodeBytes) return ALN_E_UNSUPPORTED;
   KParams kp;
   aln_status_t st = make_params(scoring, &kp);
   if (st != ALN_OK) return st;
   if (!fits_i32(kp, n, m)) return ALN_E_SCORING;
+  if (long_linear_space(n, m, flags)) {
+    LongLsPlan pl;
+    st = plan_long_ls(n, m, kLsCodeBudget, &pl);
+    if (st != ALN_OK) return st;
+    *bytes = pl.total_bytes;
+    return ALN_OK;
+  }
   LongPlan pl;
   st = plan_long(n, m, tb, &pl);
   if (st != ALN_OK) return st;
@@ -278,14 +367,20 @@ aln_status_t aln_align_long(const aln_scoring_t* scoring, const uint8_t* q, int6
                             void* workspace, size_t workspace_bytes, hipStream_t stream) {
   if (n < 0 || m < 0 || n >= (1ll << 31) || m >= (1ll << 31) || !out) return ALN_E_INVALID;
   if ((n > 0 && !q) || (m > 0 && !s)) return ALN_E_INVALID;
-  if (flags & ~(ALN_TRACEBACK | ALN_FORCE_INT32 | ALN_FORCE_INT16)) return ALN_E_INVALID;
+  if (flags & ~kLongFlags) return ALN_E_INVALID;
   const bool tb = (flags & ALN_TRACEBACK) != 0;
   if (tb && (!cigar || cigar_capacity < 0)) return ALN_E_INVALID;
-  if (tb && (n + kWfBand) / 2 * m > kMaxLongCodeBytes) return ALN_E_UNSUPPORTED;
   KParams kp;
   aln_status_t st = make_params(scoring, &kp);
   if (st != ALN_OK) return st;
   if (!fits_i32(kp, n, m)) return ALN_E_SCORING;
+  if (long_linear_space(n, m, flags)) {
+    LongLsPlan pl;
+    st = plan_long_ls(n, m, kLsCodeBudget, &pl);
+    if (st != ALN_OK) return st;
+    if (!workspace || workspace_bytes < pl.total_bytes) return ALN_E_WORKSPACE;
+    return launch_long_ls(kp, pl, q, n, s, m, out, cigar, cigar_capacity, workspace, stream);
+  }
   LongPlan pl;
   st = plan_long(n, m, tb, &pl);
   if (st != ALN_OK) return st;

@@ -492,6 +492,11 @@ aln_status_t plan_batch_i16(const KParams& kp, int64_t n_pairs, int64_t max_n, i
   pl->n_waves = (int)waves;
   pl->rowbuf_bytes = round256((size_t)(max_m + 1) * 64 * sizeof(uint2));
   pl->slab_bytes = pl->rowbuf_bytes + (tb ? round256((size_t)strips * RW * (size_t)max_m * 64 * 4) : 0);
+  if (tb) {
+    // fewer waves in flight when every wave's codes would exceed the budget (at least one workgroup)
+    const int64_t fit = kTbSlabBudget / (int64_t)pl->slab_bytes / kI16WavesPerBlock * kI16WavesPerBlock;
+    if (fit < waves) pl->n_waves = (int)(fit > kI16WavesPerBlock ? fit : kI16WavesPerBlock);
+  }
   pl->total_bytes = (size_t)pl->n_waves * pl->slab_bytes;
   return ALN_OK;
 }

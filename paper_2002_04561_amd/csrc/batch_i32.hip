@@ -33,13 +33,17 @@ __device__ __forceinline__ int64_t next_group(int* ticket, int lane) {
   return (int64_t)__shfl(g, 0, 64);
 }
 
-template <int MODE, bool AFFINE, bool TB>
+// TBK: 0 score only; 1 traceback from the optimum; 2 traceback from the end cell a forward pass found
+// (fwd[p].q_end, fwd[p].s_end): the pair is relaxed only up to that cell, whose H must equal fwd[p].score.
+template <int MODE, bool AFFINE, int TBK>
 __global__ __launch_bounds__(kBlock) void batch_i32_kernel(
     const KParams P, const uint8_t* __restrict__ q, const int64_t* __restrict__ q_off, const uint8_t* __restrict__ s,
     const int64_t* __restrict__ s_off, int64_t n_pairs, int64_t max_n, int64_t max_m, aln_result_t* __restrict__ out,
     uint32_t* __restrict__ cigar, const int64_t* __restrict__ cigar_off, char* __restrict__ ws, size_t slab_bytes,
     size_t rowbuf_bytes, const int* __restrict__ idx, const int* __restrict__ idx_count, uint32_t extra_flags,
-    int* __restrict__ ticket) {
+    int* __restrict__ ticket, const aln_result_t* __restrict__ fwd) {
+  constexpr bool TB = TBK != 0;
+  constexpr bool FIXED = TBK == 2;
   __shared__ int32_t tab[kTab * kTab];
   for (int k = threadIdx.x; k < kTab * kTab; k += blockDim.x) {
     const int a = k / kTab, b = k % kTab;
@@ -69,6 +73,7 @@ __global__ __launch_bounds__(kBlock) void batch_i32_kernel(
     int64_t qb = 0, sb = 0;
     int n = 0, m = 0;
     uint32_t flags = 0;
+    aln_result_t fw{};
     if (active) {
       qb = q_off[p];
       sb = s_off[p];
@@ -78,6 +83,20 @@ __global__ __launch_bounds__(kBlock) void batch_i32_kernel(
       } else {
         n = (int)nn;
         m = (int)mm;
+      }
+      if (FIXED) {
+        // the forward pass's result: its failures carry over; otherwise only the rectangle up to its
+        // end cell is relaxed (the values there are those of the whole matrix)
+        fw = fwd[p];
+        flags |= fw.flags & (ALN_RES_BAD_CODE | ALN_RES_TOO_LONG | ALN_RES_DEVICE_ERROR);
+        if (!flags && (fw.q_end < 0 || fw.q_end > n || fw.s_end < 0 || fw.s_end > m)) flags |= ALN_RES_BAD_END;
+        if (flags) {
+          n = 0;
+          m = 0;
+        } else {
+          n = fw.q_end;
+          m = fw.s_end;
+        }
       }
     }
     const int nmax = wave_max_i32(n), mmax = wave_max_i32(m);
@@ -162,14 +181,14 @@ __global__ __launch_bounds__(kBlock) void batch_i32_kernel(
             const uint32_t fe = AFFINE ? (uint32_t)(hlo + goe != ff) : 0u;
             word |= (src | (ee << 2) | (fe << 3)) << (4 * r);
           }
-          if (MODE == ALN_LOCAL) {
+          if (MODE == ALN_LOCAL && !FIXED) {
             if (h > bv[r]) {
               bv[r] = h;
               bjr[r] = j;
             }
           } else {
             if (j == m) cap[r] = h;
-            if (MODE == ALN_SEMIGLOBAL && r == rn) hn = h;
+            if (MODE == ALN_SEMIGLOBAL && !FIXED && r == rn) hn = h;
           }
           f[r] = ff;
           hl[r] = h;
@@ -179,7 +198,7 @@ __global__ __launch_bounds__(kBlock) void batch_i32_kernel(
         }
         if (k + 1 < strips) rowbuf[(size_t)j * 64 + lane] = make_int2(hup, eup);
         if (TB) dirs[((size_t)k * (size_t)max_m + (size_t)(j - 1)) * 64 + lane] = word;
-        if (MODE == ALN_SEMIGLOBAL && has_n && j <= m && hn > brow) {
+        if (MODE == ALN_SEMIGLOBAL && !FIXED && has_n && j <= m && hn > brow) {
           brow = hn;
           browj = j;
         }
@@ -188,7 +207,9 @@ __global__ __launch_bounds__(kBlock) void batch_i32_kernel(
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         const int i = i0 + 1 + r;
-        if (MODE == ALN_LOCAL) {
+        if (FIXED) {
+          if (i == n) hfinal = cap[r];
+        } else if (MODE == ALN_LOCAL) {
           if (bv[r] > best) {
             best = bv[r];
             bi = i;
@@ -206,7 +227,16 @@ __global__ __launch_bounds__(kBlock) void batch_i32_kernel(
       }
     }
 
-    if (MODE == ALN_SEMIGLOBAL) {
+    if (FIXED) {
+      // H at the given end cell; on row 0 or column 0 it is the mode's border value
+      bi = n;
+      bj = m;
+      if (n == 0 || m == 0)
+        best = (MODE == ALN_GLOBAL && n + m > 0) ? go + (n + m) * ge : 0;
+      else
+        best = hfinal;
+      if (active && !flags && best != fw.score) flags |= ALN_RES_BAD_END;
+    } else if (MODE == ALN_SEMIGLOBAL) {
       if (n == 0 || m == 0) {
         best = 0;
         bi = 0;
@@ -258,35 +288,47 @@ __global__ __launch_bounds__(kBlock) void batch_i32_kernel(
   }
 }
 
-template <int MODE, bool AFFINE, bool TB>
+template <int MODE, bool AFFINE, int TBK>
 void launch_one(const KParams& kp, const BatchPlan& pl, const uint8_t* q, const int64_t* q_off, const uint8_t* s,
                 const int64_t* s_off, aln_result_t* out, uint32_t* cigar, const int64_t* cigar_off, void* ws,
-                const int* idx, const int* idx_count, uint32_t extra_flags, int* ticket, hipStream_t stream) {
+                const int* idx, const int* idx_count, uint32_t extra_flags, int* ticket, const aln_result_t* fwd,
+                hipStream_t stream) {
   const size_t slab = pl.rowbuf_bytes + pl.dirs_bytes;
   const int blocks = (pl.n_waves + kWavesPerBlock - 1) / kWavesPerBlock;
-  ProfScope prof(TB ? "batch_i32_traceback" : "batch_i32_score", stream);
-  hipLaunchKernelGGL((batch_i32_kernel<MODE, AFFINE, TB>), dim3(blocks), dim3(kBlock), 0, stream, kp, q, q_off, s,
+  ProfScope prof(TBK == 2 ? "batch_i32_traceback_from_end" : (TBK ? "batch_i32_traceback" : "batch_i32_score"),
+                 stream);
+  hipLaunchKernelGGL((batch_i32_kernel<MODE, AFFINE, TBK>), dim3(blocks), dim3(kBlock), 0, stream, kp, q, q_off, s,
                      s_off, pl.n_pairs, pl.max_n, pl.max_m, out, cigar, cigar_off, static_cast<char*>(ws), slab,
-                     pl.rowbuf_bytes, idx, idx_count, extra_flags, ticket);
+                     pl.rowbuf_bytes, idx, idx_count, extra_flags, ticket, fwd);
+}
+
+template <int MODE, bool AFFINE>
+void launch_tb(const KParams& kp, const BatchPlan& pl, const uint8_t* q, const int64_t* q_off, const uint8_t* s,
+               const int64_t* s_off, bool tb, aln_result_t* out, uint32_t* cigar, const int64_t* cigar_off, void* ws,
+               const int* idx, const int* idx_count, uint32_t extra_flags, int* ticket, const aln_result_t* fwd,
+               hipStream_t stream) {
+  if (fwd)
+    launch_one<MODE, AFFINE, 2>(kp, pl, q, q_off, s, s_off, out, cigar, cigar_off, ws, idx, idx_count, extra_flags,
+                                ticket, fwd, stream);
+  else if (tb)
+    launch_one<MODE, AFFINE, 1>(kp, pl, q, q_off, s, s_off, out, cigar, cigar_off, ws, idx, idx_count, extra_flags,
+                                ticket, nullptr, stream);
+  else
+    launch_one<MODE, AFFINE, 0>(kp, pl, q, q_off, s, s_off, out, cigar, cigar_off, ws, idx, idx_count, extra_flags,
+                                ticket, nullptr, stream);
 }
 
 template <int MODE>
 void launch_mode(const KParams& kp, const BatchPlan& pl, const uint8_t* q, const int64_t* q_off, const uint8_t* s,
                  const int64_t* s_off, bool tb, aln_result_t* out, uint32_t* cigar, const int64_t* cigar_off,
                  void* ws, const int* idx, const int* idx_count, uint32_t extra_flags, int* ticket,
-                 hipStream_t stream) {
-  const bool affine = kp.go != 0;
-  if (affine) {
-    if (tb)
-      launch_one<MODE, true, true>(kp, pl, q, q_off, s, s_off, out, cigar, cigar_off, ws, idx, idx_count, extra_flags, ticket, stream);
-    else
-      launch_one<MODE, true, false>(kp, pl, q, q_off, s, s_off, out, cigar, cigar_off, ws, idx, idx_count, extra_flags, ticket, stream);
-  } else {
-    if (tb)
-      launch_one<MODE, false, true>(kp, pl, q, q_off, s, s_off, out, cigar, cigar_off, ws, idx, idx_count, extra_flags, ticket, stream);
-    else
-      launch_one<MODE, false, false>(kp, pl, q, q_off, s, s_off, out, cigar, cigar_off, ws, idx, idx_count, extra_flags, ticket, stream);
-  }
+                 const aln_result_t* fwd, hipStream_t stream) {
+  if (kp.go != 0)
+    launch_tb<MODE, true>(kp, pl, q, q_off, s, s_off, tb, out, cigar, cigar_off, ws, idx, idx_count, extra_flags,
+                          ticket, fwd, stream);
+  else
+    launch_tb<MODE, false>(kp, pl, q, q_off, s, s_off, tb, out, cigar, cigar_off, ws, idx, idx_count, extra_flags,
+                           ticket, fwd, stream);
 }
 
 size_t round256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -311,6 +353,12 @@ aln_status_t plan_batch_i32(const KParams& kp, int64_t n_pairs, int64_t max_n, i
   pl.n_waves = (int32_t)waves;
   pl.rowbuf_bytes = round256((size_t)(max_m + 1) * 64 * sizeof(int2));
   pl.dirs_bytes = traceback ? round256((size_t)pl.strips * (size_t)max_m * 64 * sizeof(uint32_t)) : 0;
+  if (traceback) {
+    // fewer waves in flight when every wave's codes would exceed the budget (at least one workgroup)
+    const int64_t slab = (int64_t)(pl.rowbuf_bytes + pl.dirs_bytes);
+    const int64_t fit = kTbSlabBudget / slab / kWavesPerBlock * kWavesPerBlock;
+    if (fit < waves) pl.n_waves = (int32_t)(fit > kWavesPerBlock ? fit : kWavesPerBlock);
+  }
   pl.total_bytes = (size_t)pl.n_waves * (pl.rowbuf_bytes + pl.dirs_bytes);
   *plan = pl;
   return ALN_OK;
@@ -319,17 +367,20 @@ aln_status_t plan_batch_i32(const KParams& kp, int64_t n_pairs, int64_t max_n, i
 aln_status_t launch_batch_i32(const KParams& kp, const BatchPlan& pl, const uint8_t* q, const int64_t* q_off,
                               const uint8_t* s, const int64_t* s_off, bool tb, aln_result_t* out, uint32_t* cigar,
                               const int64_t* cigar_off, void* ws, const int* idx, const int* idx_count,
-                              uint32_t extra_flags, int* ticket, hipStream_t stream) {
+                              uint32_t extra_flags, int* ticket, hipStream_t stream, const aln_result_t* fwd) {
   if (pl.n_pairs == 0) return ALN_OK;
   switch (kp.mode) {
     case ALN_GLOBAL:
-      launch_mode<ALN_GLOBAL>(kp, pl, q, q_off, s, s_off, tb, out, cigar, cigar_off, ws, idx, idx_count, extra_flags, ticket, stream);
+      launch_mode<ALN_GLOBAL>(kp, pl, q, q_off, s, s_off, tb, out, cigar, cigar_off, ws, idx, idx_count, extra_flags,
+                              ticket, fwd, stream);
       break;
     case ALN_LOCAL:
-      launch_mode<ALN_LOCAL>(kp, pl, q, q_off, s, s_off, tb, out, cigar, cigar_off, ws, idx, idx_count, extra_flags, ticket, stream);
+      launch_mode<ALN_LOCAL>(kp, pl, q, q_off, s, s_off, tb, out, cigar, cigar_off, ws, idx, idx_count, extra_flags,
+                             ticket, fwd, stream);
       break;
     default:
-      launch_mode<ALN_SEMIGLOBAL>(kp, pl, q, q_off, s, s_off, tb, out, cigar, cigar_off, ws, idx, idx_count, extra_flags, ticket, stream);
+      launch_mode<ALN_SEMIGLOBAL>(kp, pl, q, q_off, s, s_off, tb, out, cigar, cigar_off, ws, idx, idx_count,
+                                  extra_flags, ticket, fwd, stream);
       break;
   }
   return hipGetLastError() == hipSuccess ? ALN_OK : ALN_E_DEVICE;

@@ -32,6 +32,10 @@ struct KParams {
   int8_t sig[kMaxAlphabet * kMaxAlphabet];  // row-major sigma(q, s) over the real alphabet
 };
 
+// Traceback slabs of the one-pair-per-lane kernels hold every cell's code for the waves in flight; a batch
+// of large pairs runs fewer waves rather than asking for more than this.
+constexpr int64_t kTbSlabBudget = (int64_t)8 << 30;
+
 constexpr int64_t kSpinDevDefault = 1ll << 22;  // ~0.1-0.5 s of polling device memory
 constexpr int64_t kSpinLdsDefault = 1ll << 26;  // ~1-2 s of polling LDS
 
@@ -87,6 +91,9 @@ struct WfWs {
   int* n_pairs;      // pairs in the table (device value)
   int* error;        // set when a bounded wait gives up
   uint16_t* codes;   // traceback: [band][lane][column] codes of 4 rows (4 bits each)
+  int2* ckcols;      // checkpointed forward pass (one pair), else null: [k][row - 1] Hb and Fb of column
+                     // (k + 1) * kTileCols; its row slots hold every group's bottom row
+  int64_t ck_ld;     // rows of a checkpoint column (a multiple of the band height)
 };
 
 struct WfOffsets {
@@ -103,6 +110,8 @@ struct LongPlan {
 
 constexpr int kWfR = 4;             // rows per lane in the wavefront engine
 constexpr int kWfBand = 64 * kWfR;  // rows per band
+constexpr int kTileCols = 2048;     // linear-space traceback: columns of a recomputed tile (a power of 2)
+constexpr int kTileRows = 4 * kWfBand;  // rows of a recomputed tile: one workgroup's 4 bands
 
 aln_status_t make_params(const aln_scoring_t* sc, KParams* kp);
 int device_cu_count();
@@ -113,7 +122,8 @@ aln_status_t plan_batch_i32(const KParams& kp, int64_t n_pairs, int64_t max_n, i
 aln_status_t launch_batch_i32(const KParams& kp, const BatchPlan& plan, const uint8_t* q, const int64_t* q_off,
                               const uint8_t* s, const int64_t* s_off, bool traceback, aln_result_t* out,
                               uint32_t* cigar, const int64_t* cigar_off, void* ws, const int* idx,
-                              const int* idx_count, uint32_t extra_flags, int* ticket, hipStream_t stream);
+                              const int* idx_count, uint32_t extra_flags, int* ticket, hipStream_t stream,
+                              const aln_result_t* fwd = nullptr);
 
 // batch_i16.hip
 struct BatchPlan16 {
@@ -157,6 +167,24 @@ aln_status_t launch_wf_i32(const KParams& kp, const WfWs& W, const uint8_t* q, c
                            int max_waves, bool grouped, bool tb, bool p16, uint32_t* cigar, int64_t cigar_cap,
                            hipStream_t stream);
 aln_status_t plan_long(int64_t n, int64_t m, bool tb, LongPlan* plan);
+void launch_single_pair(const WfWs& W, int n, int m, hipStream_t stream);
+
+// tb_tiles.hip: linear-space traceback of one pair (checkpointed forward pass, tiles relaxed again)
+struct LongLsPlan {
+  int64_t nb;        // bands of the forward pass
+  int n_waves;       // its waves
+  WfOffsets off;     // its workspace (row slots: one per group of 4 bands)
+  int64_t ck_ld;     // rows of a checkpoint column
+  int strips;        // tiles across the columns
+  int64_t seg_rows;  // rows of a segment
+  int nseg;          // segments
+  size_t off_ckcols, off_codes, off_walk, total_bytes;
+};
+constexpr int64_t kLsCodeBudget = (int64_t)4 << 30;  // codes of one segment
+aln_status_t plan_long_ls(int64_t n, int64_t m, int64_t code_budget, LongLsPlan* plan);
+aln_status_t launch_long_ls(const KParams& kp, const LongLsPlan& plan, const uint8_t* q, int64_t n, const uint8_t* s,
+                            int64_t m, aln_result_t* out, uint32_t* cigar, int64_t cigar_cap, void* ws,
+                            hipStream_t stream);
 aln_status_t launch_long(const KParams& kp, const LongPlan& plan, const uint8_t* q, int64_t n, const uint8_t* s,
                          int64_t m, aln_result_t* out, uint32_t* cigar, int64_t cigar_cap, void* ws,
                          hipStream_t stream);

@@ -23,6 +23,7 @@
 
 #include "internal.h"
 #include "walk.h"
+#include "walk_wave.h"
 
 extern "C" __device__ __attribute__((const)) int __ockl_wfred_max_i32(int);  // maximum over the wave
 
@@ -471,7 +472,10 @@ __global__ __launch_bounds__(kWfBlockAlone) void wf_i32_kernel(const KParams P, 
 //   Fb(i,j) = max(Fb(i,j-1) + ge, Hb(i,j-1) + go + ge)
 //   Hb(i,j) = max(Hb(i-1,j-1) + sigma - ge, Eb, Fb [, -i*ge for local])
 // which is Eqs. (1), (4), (5) with every term shifted by the same per-row constant.
-template <int MODE, bool AFFINE, int PROF, bool TB, int R, bool P16>
+// CKPT: also store checkpoints for a linear-space traceback (one pair, groups aligned with its bands):
+// every group's bottom row stays in its own row slot instead of two rotating ones, and every
+// kTileCols-th column's H and F of all rows go to W.ckcols.
+template <int MODE, bool AFFINE, int PROF, bool TB, int R, bool P16, bool CKPT>
 __global__ __launch_bounds__(kWfBlock) void wf_i32_group_kernel(const KParams P, const uint8_t* __restrict__ Q,
                                                           const uint8_t* __restrict__ S, WfWs W) {
   static_assert(PROF != kProfLane || R == 4, "a lane profile word holds 4 rows");
@@ -487,6 +491,7 @@ __global__ __launch_bounds__(kWfBlock) void wf_i32_group_kernel(const KParams P,
   __shared__ int s_err;
   extern __shared__ uint32_t lprof[];        // kProfLane: [wave][letter][lane], alphabet letters
   static_assert(!P16 || (MODE == ALN_LOCAL && PROF == kProfReg && !TB && R == 4), "packed bands: local, score only");
+  static_assert(!CKPT || (!TB && !P16 && R == 4), "checkpoints: 32-bit score-only bands");
   // packed bands: the upper half's bottom row (absolute H, E) on its way to the lower half
   __shared__ int2 dline[P16 ? kWfWavesPerBlock : 1][P16 ? kDelayRing : 1];
   for (int k = threadIdx.x; k < kTab * kTab; k += blockDim.x) {
@@ -542,7 +547,8 @@ __global__ __launch_bounds__(kWfBlock) void wf_i32_group_kernel(const KParams P,
       if (b > 0) {
         in_on = true;
         m_in = a.m;
-        src = W.rows + a.row_off + (int64_t)((b + 1) & 1) * ((int64_t)a.m + 1);
+        const int64_t slot = CKPT ? b / kWfWavesPerBlock - 1 : ((b + 1) & 1);
+        src = W.rows + a.row_off + slot * ((int64_t)a.m + 1);
       }
     }
     if (tout < n_items) {
@@ -551,7 +557,8 @@ __global__ __launch_bounds__(kWfBlock) void wf_i32_group_kernel(const KParams P,
       if (b + 1 < a.nb) {
         out_on = true;
         m_out = a.m;
-        dst = W.rows + a.row_off + (int64_t)(b & 1) * ((int64_t)a.m + 1);
+        const int64_t slot = CKPT ? b / kWfWavesPerBlock : (b & 1);
+        dst = W.rows + a.row_off + slot * ((int64_t)a.m + 1);
       }
     }
     int in_done = 0, out_done = 0, seen = 0;
@@ -1044,8 +1051,9 @@ __global__ __launch_bounds__(kWfBlock) void wf_i32_group_kernel(const KParams P,
         st_e[lane] = te;
         st_c[lane] = sreg;
       }
-      // One step: lane l relaxes column j = t - l + 1 for its R rows.
-      auto step = [&](int t, int in_top_h, int in_top_e, int in_top_c, auto checked, int32_t* hk) {
+      // One step: lane l relaxes column j = t - l + 1 for its R rows.  With ckc (checkpointing, wave-uniform)
+      // a lane whose column is a multiple of kTileCols also stores its rows' H and F there.
+      auto step = [&](int t, int in_top_h, int in_top_e, int in_top_c, auto checked, int32_t* hk, bool ckc) {
         const int j = t - lane + 1;
         const int in_h = dpp_shr1(in_top_h, bot_h);
         const int in_e = dpp_shr1(in_top_e, bot_e);
@@ -1096,6 +1104,12 @@ __global__ __launch_bounds__(kWfBlock) void wf_i32_group_kernel(const KParams P,
             brow = hn;
             browj = j;
           }
+          if (CKPT && ckc && (j & (kTileCols - 1)) == 0 && j >= kTileCols && j < m) {
+            // rows irow0+1..irow0+4 of column j: Hb and Fb, 32 contiguous bytes
+            int4* dst = reinterpret_cast<int4*>(W.ckcols + (int64_t)(j / kTileCols - 1) * W.ck_ld + irow0);
+            dst[0] = make_int4(hl[0], f[0], hl[1], f[1]);
+            dst[1] = make_int4(hl[2], f[2], hl[3], f[3]);
+          }
           bot_h = hup;
           bot_e = eup;
           diag = in_h;
@@ -1111,10 +1125,20 @@ __global__ __launch_bounds__(kWfBlock) void wf_i32_group_kernel(const KParams P,
         if (t0 >= 63 && t0 + 3 < m) {
           // every lane is inside the matrix: no range test; local optima are tracked per 4 steps
           int32_t hk[4][R];
-          step(t0, vh.x, ve.x, vc.x, std::false_type(), hk[0]);
-          step(t0 + 1, vh.y, ve.y, vc.y, std::false_type(), hk[1]);
-          step(t0 + 2, vh.z, ve.z, vc.z, std::false_type(), hk[2]);
-          step(t0 + 3, vh.w, ve.w, vc.w, std::false_type(), hk[3]);
+          // some lane's column in these 4 steps is a multiple of kTileCols only when (t0 + 1) mod
+          // kTileCols is below 64 or within 3 of kTileCols (a wave-uniform test)
+          const int u = (t0 + 1) & (kTileCols - 1);
+          if (CKPT && (u < 64 || u > kTileCols - 4)) {
+            step(t0, vh.x, ve.x, vc.x, std::false_type(), hk[0], true);
+            step(t0 + 1, vh.y, ve.y, vc.y, std::false_type(), hk[1], true);
+            step(t0 + 2, vh.z, ve.z, vc.z, std::false_type(), hk[2], true);
+            step(t0 + 3, vh.w, ve.w, vc.w, std::false_type(), hk[3], true);
+          } else {
+            step(t0, vh.x, ve.x, vc.x, std::false_type(), hk[0], false);
+            step(t0 + 1, vh.y, ve.y, vc.y, std::false_type(), hk[1], false);
+            step(t0 + 2, vh.z, ve.z, vc.z, std::false_type(), hk[2], false);
+            step(t0 + 3, vh.w, ve.w, vc.w, std::false_type(), hk[3], false);
+          }
           if (MODE == ALN_LOCAL) {
             int32_t mk[R];
             bool imp = false;
@@ -1137,10 +1161,10 @@ __global__ __launch_bounds__(kWfBlock) void wf_i32_group_kernel(const KParams P,
             }
           }
         } else {
-          step(t0, vh.x, ve.x, vc.x, std::true_type(), nullptr);
-          step(t0 + 1, vh.y, ve.y, vc.y, std::true_type(), nullptr);
-          step(t0 + 2, vh.z, ve.z, vc.z, std::true_type(), nullptr);
-          step(t0 + 3, vh.w, ve.w, vc.w, std::true_type(), nullptr);
+          step(t0, vh.x, ve.x, vc.x, std::true_type(), nullptr, CKPT);
+          step(t0 + 1, vh.y, ve.y, vc.y, std::true_type(), nullptr, CKPT);
+          step(t0 + 2, vh.z, ve.z, vc.z, std::true_type(), nullptr, CKPT);
+          step(t0 + 3, vh.w, ve.w, vc.w, std::true_type(), nullptr, CKPT);
         }
       }
       // lanes 64-BLK.. hold lane 63's outputs of steps tb..tb+BLK-1, i.e. columns tb-62..tb+BLK-63
@@ -1217,163 +1241,6 @@ __global__ __launch_bounds__(kWfBlock) void wf_i32_group_kernel(const KParams P,
 }
 
 // One wave per pair: reduces the pair's band optima into its aln_result_t.
-constexpr int kWalkGroups = 32;  // row groups (of kWfR rows) in a traceback window
-constexpr int kWalkCols = 128;   // columns in a traceback window
-
-// Traceback of one wavefront pair by a whole wave: the walk of walk_back (the canonical rule of
-// walk.h, which the one-pair-per-lane kernels run per lane), with the codes read from an LDS window of
-// kWalkGroups row groups x kWalkCols columns ending at the current cell, and diagonal runs taken up to
-// 64 cells at a time: lane t looks at cell (i - t, j - t), and the first lane whose cell is not a
-// diagonal move, or lies outside the window or the matrix, ends the run.  Gap runs are taken the same
-// way along their column or row.  Every lane runs the same walk and stores the same runs.  *stuck is
-// set if the walk did not end within 2 (i + j) + 64 turns, which a valid code array never allows.
-template <int MODE>
-__device__ void walk_wave(const uint16_t* __restrict__ codes, int m, int i, int j, uint16_t* __restrict__ win,
-                          int lane, uint32_t* __restrict__ cig, int64_t cap, int* q_begin, int* s_begin, int* n_runs,
-                          bool* stuck) {
-  // Every lane holds the same walk state; saying so lets the compiler keep it in scalar registers
-  // and branch on it with scalar branches.
-  i = __builtin_amdgcn_readfirstlane(i);
-  j = __builtin_amdgcn_readfirstlane(j);
-  // The window holds row groups g0-kWalkGroups+1..g0 and columns c0-kWalkCols+1..c0; it is loaded at
-  // the walk's cell, in row group g0 and column c0.  The walk only moves up and left, so every later
-  // cell is inside it as long as it lies at or below row ilo and at or right of column jlo (the
-  // window's first row and column inside the matrix).  Before the first load nothing is inside.
-  int g0 = 0, c0 = 0, ilo = 0x7fffffff, jlo = 0x7fffffff;
-  auto load = [&](int ii, int jj) {
-    g0 = (ii - 1) / kWfR;
-    c0 = jj;
-    ilo = max(1, (g0 - kWalkGroups + 1) * kWfR + 1);
-    jlo = max(1, c0 - kWalkCols + 1);
-    // every load of the window is issued before the first LDS write, so the reload costs one
-    // memory latency rather than one per code
-    // A window cell outside the matrix (row group < 0 or column < 1) loads the in-bounds cell
-    // (g0, c0) instead; it lies before row ilo or column jlo, so code() never reads it.  The loads
-    // carry no branches, so all of them stay in flight together.
-    constexpr int kPer = kWalkGroups * kWalkCols / 64;
-    uint32_t v[kPer];
-#pragma unroll
-    for (int u = 0; u < kPer; ++u) {
-      const int k = lane + 64 * u;
-      const int gg = g0 - k / kWalkCols, cc = c0 - k % kWalkCols;
-      const bool ok = gg >= 0 && cc >= 1;
-      v[u] = codes[(size_t)(ok ? gg : g0) * (size_t)m + (size_t)((ok ? cc : c0) - 1)];
-    }
-#pragma unroll
-    for (int u = 0; u < kPer; ++u) win[lane + 64 * u] = (uint16_t)v[u];
-    asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)" ::: "memory");  // the window is in LDS before it is read
-  };
-  // the code of a cell inside the window
-  auto code = [&](int ii, int jj) -> uint32_t {
-    const unsigned r = (unsigned)(ii - 1);
-    const uint32_t w = win[(g0 - (int)(r / kWfR)) * kWalkCols + (c0 - jj)];
-    return (w >> (4 * (r % kWfR))) & 15u;
-  };
-  int64_t runs = 0;
-  uint32_t cur_op = 0xffu, cur_len = 0;
-  auto push = [&](uint32_t op, uint32_t len) {
-    if (op == cur_op) {
-      cur_len += len;
-      return;
-    }
-    if (cur_len) {
-      if (runs < cap) cig[runs] = (cur_len << 4) | cur_op;
-      ++runs;
-    }
-    cur_op = op;
-    cur_len = len;
-  };
-  int state = 0;  // 0 = H, 1 = E, 2 = F
-  int64_t turns = 2 * ((int64_t)i + j) + 64;
-  for (; turns > 0; --turns) {
-    if (state == 0) {
-      if (i == 0 || j == 0) {
-        if (MODE == ALN_GLOBAL) {
-          if (j > 0) push(ALN_CIGAR_D, (uint32_t)j);
-          if (i > 0) push(ALN_CIGAR_I, (uint32_t)i);
-          i = 0;
-          j = 0;
-        }
-        break;
-      }
-      if (i < ilo || j < jlo) load(i, j);
-      // lanes t <= lim look at cells inside the window; the others read (i, j) and count as a
-      // non-diagonal code, which ends the run
-      const int lim = min(i - ilo, j - jlo);
-      const bool in = lane <= lim;
-      const int t = in ? lane : 0;
-      const uint32_t ct = code(i - t, j - t);
-      const uint32_t pc = in ? ct : 3u;
-      const unsigned long long stop = __builtin_amdgcn_ballot_w64((pc & 3u) != 0u);
-      const int k = stop ? __builtin_ctzll(stop) : 64;
-      if (k > 0) {
-        push(ALN_CIGAR_M, (uint32_t)k);
-        i -= k;
-        j -= k;
-        continue;
-      }
-      // lane 0 looked at (i, j) itself, which the window holds; its code also gives the first gap
-      // step, taken below without reading the cell again
-      const uint32_t c = (uint32_t)__builtin_amdgcn_readfirstlane((int)pc);
-      if ((c & 3u) == 3u) break;
-      state = (int)(c & 3u);
-      if (state == 1) {
-        push(ALN_CIGAR_I, 1);
-        if (!(c & 4u) || i == 1) state = 0;
-        --i;
-      } else {
-        push(ALN_CIGAR_D, 1);
-        if (!(c & 8u) || j == 1) state = 0;
-        --j;
-      }
-    } else {
-      // A gap run, up to 64 steps at a time: lane t looks at the t-th cell of the run.  The run goes
-      // on through a cell whose extension bit is set and which is not in row (column) 1; the first
-      // cell that ends it is stepped through and returns the walk to H, unless it lies outside the
-      // window, where the walk stops short of it and reloads.
-      if (i < ilo || j < jlo) load(i, j);
-      const bool vert = state == 1;
-      const int lim = vert ? i - ilo : j - jlo;  // lanes t <= lim look at cells inside the window
-      const bool in = lane <= lim;
-      const int t = in ? lane : 0;
-      const int ii = vert ? i - t : i, jj = vert ? j : j - t;
-      const uint32_t pc = code(ii, jj);
-      const bool more = in && (pc & (vert ? 4u : 8u)) != 0u && (vert ? ii : jj) > 1;
-      const unsigned long long stop = __builtin_amdgcn_ballot_w64(!more);
-      const int k = stop ? __builtin_ctzll(stop) : 64;
-      const bool ends = k < 64 && k <= lim;
-      const int steps = k + (ends ? 1 : 0);
-      push(vert ? ALN_CIGAR_I : ALN_CIGAR_D, (uint32_t)steps);
-      if (vert)
-        i -= steps;
-      else
-        j -= steps;
-      if (ends) state = 0;
-    }
-  }
-  *stuck = turns <= 0;
-  if (cur_len) {
-    if (runs < cap) cig[runs] = (cur_len << 4) | cur_op;
-    ++runs;
-  }
-  if (runs <= cap) {
-    // The runs were stored last to first; reverse them with the whole wave.  Lane l swaps the pairs
-    // (a, runs-1-a) with a = l, l+64, ...: no two lanes touch the same run, and each lane's loads
-    // are its own earlier stores' addresses only through the walk above, which has completed.
-    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-    const int64_t half = runs / 2;
-    for (int64_t a = lane; a < half; a += 64) {
-      const int64_t b = runs - 1 - a;
-      const uint32_t x = cig[a], y = cig[b];
-      cig[a] = y;
-      cig[b] = x;
-    }
-  }
-  *q_begin = i;
-  *s_begin = j;
-  *n_runs = (int)runs;
-}
-
 template <int MODE, bool TB>
 __global__ __launch_bounds__(256) void wf_finish_kernel(const KParams P, WfWs W, aln_result_t* __restrict__ out,
                                                         uint32_t* __restrict__ cigar, int64_t cigar_cap) {
@@ -1437,16 +1304,16 @@ __global__ __launch_bounds__(256) void wf_finish_kernel(const KParams P, WfWs W,
     }
     if (TB && r.flags == 0) {
       // The codes form a [row group][column] array of 16-bit words, 4 rows per word (band bb, lane L
-      // is row group bb * 64 + L); walk_wave walks them with the whole wave.
-      int qbeg, sbeg, runs;
-      bool stuck = false;
-      walk_wave<MODE>(W.codes + pr.code_off, m, r.q_end, r.s_end, walk_win[threadIdx.x >> 6], lane, cigar, cigar_cap,
-                      &qbeg, &sbeg, &runs, &stuck);
-      r.q_begin = qbeg;
-      r.s_begin = sbeg;
-      r.cigar_len = runs;
+      // is row group bb * 64 + L); walk_core walks them with the whole wave.
+      WalkState S;
+      walk_start(S, r.q_end, r.s_end);
+      walk_core<MODE>(W.codes + pr.code_off, m, 0, S, walk_win[threadIdx.x >> 6], lane, cigar, cigar_cap);
+      const int64_t runs = walk_finish(S, lane, cigar, cigar_cap);
+      r.q_begin = S.i;
+      r.s_begin = S.j;
+      r.cigar_len = (int)runs;
       if (runs > cigar_cap) r.flags |= ALN_RES_CIGAR_TRUNC;
-      if (stuck) r.flags |= ALN_RES_DEVICE_ERROR;
+      if (S.stuck) r.flags |= ALN_RES_DEVICE_ERROR;
     }
     if (lane == 0) out[pr.out_idx] = r;
   }
@@ -1510,14 +1377,20 @@ void launch_wf_t(const KParams& kp, const uint8_t* q, const uint8_t* s, const Wf
   constexpr bool kCanPack = MODE == ALN_LOCAL && PROF == kProfReg && !TB;
   if (kCanPack && grouped && p16 && p16_exact(kp)) {
     ProfScope prof("wavefront_p16", stream);
-    hipLaunchKernelGGL((wf_i32_group_kernel<MODE, AFFINE, PROF, TB, kWfR, kCanPack>), dim3(blocks), dim3(kWfBlock),
-                       lds, stream, kp, q, s, W);
+    hipLaunchKernelGGL((wf_i32_group_kernel<MODE, AFFINE, PROF, TB, kWfR, kCanPack, false>), dim3(blocks),
+                       dim3(kWfBlock), lds, stream, kp, q, s, W);
+    return;
+  }
+  if (!TB && W.ckcols) {
+    ProfScope prof("wavefront_i32_checkpoints", stream);
+    hipLaunchKernelGGL((wf_i32_group_kernel<MODE, AFFINE, PROF, false, kWfR, false, !TB>), dim3(blocks),
+                       dim3(kWfBlock), lds, stream, kp, q, s, W);
     return;
   }
   ProfScope prof(TB ? "wavefront_i32_traceback" : "wavefront_i32", stream);
   if (grouped)
-    hipLaunchKernelGGL((wf_i32_group_kernel<MODE, AFFINE, PROF, TB, kWfR, false>), dim3(blocks), dim3(kWfBlock), lds,
-                       stream, kp, q, s, W);
+    hipLaunchKernelGGL((wf_i32_group_kernel<MODE, AFFINE, PROF, TB, kWfR, false, false>), dim3(blocks),
+                       dim3(kWfBlock), lds, stream, kp, q, s, W);
   else
     hipLaunchKernelGGL((wf_i32_kernel<MODE, AFFINE, PROF, TB, kWfR>), dim3(blocks), dim3(kWfBlockAlone), lds,
                        stream, kp, q, s, W);
@@ -1598,6 +1471,8 @@ WfWs wf_view(void* base_, const WfOffsets& o) {
   W.n_pairs = reinterpret_cast<int*>(base + o.misc + 16);
   W.error = reinterpret_cast<int*>(base + o.misc + 20);
   W.codes = reinterpret_cast<uint16_t*>(base + o.codes);
+  W.ckcols = nullptr;
+  W.ck_ld = 0;
   return W;
 }
 
@@ -1635,6 +1510,10 @@ aln_status_t plan_long(int64_t n, int64_t m, bool tb, LongPlan* pl) {
   const int64_t code_words = tb ? pl->nb * 64 * m : 0;
   pl->total_bytes = wf_layout(1, pl->nb, 2 * (m + 1), code_words, &pl->off);
   return ALN_OK;
+}
+
+void launch_single_pair(const WfWs& W, int n, int m, hipStream_t stream) {
+  hipLaunchKernelGGL(wf_single_pair_kernel, dim3(1), dim3(64), 0, stream, W, n, m, kWfBand);
 }
 
 aln_status_t launch_long(const KParams& kp, const LongPlan& pl, const uint8_t* q, int64_t n, const uint8_t* s,
