@@ -15,6 +15,8 @@ Workloads (synth/__init__.py has the recipes):
   reads    1,048,576 read/window pairs, semi-global affine (-5/-2, +1/-4), CIGAR for every pair
   long     1 pair 262144 x 262144 DNA, local affine (-3/-1, +2/-3), score + end cell
   long_tb  the same pair with its CIGAR
+  long_tb_393216  a 393216 x 393216 pair made the same way, with its CIGAR: its 4-bit codes would take 72 GiB,
+           so the traceback runs in linear space
   nw1k     1 pair 1000 x 1000 DNA, global linear (+2/-1, gap -1), CIGAR
   serve    only the request stream through the continuous-batching server (paper_2002_04561_amd/serve.py):
            a Poisson stream of 80% read/window pairs with CIGARs, 19% protein pairs (lengths log-uniform
@@ -50,6 +52,9 @@ def make_workload(name, pairs=None):
     if name == "long_tb":
         import dataclasses
         return dataclasses.replace(synth.long_dna_local(), traceback=True)
+    if name == "long_tb_393216":
+        import dataclasses
+        return dataclasses.replace(synth.long_dna_local(n=393216), traceback=True)
     if name == "reads":
         return synth.reads_semiglobal(n_pairs=pairs or (1 << 20))
     if name == "protein":
@@ -127,7 +132,8 @@ def run_cpu_baseline(w, budget_s=20.0):
                 k2, w.n_pairs, float(csum[k2 - 1]), "with traceback" if w.traceback else "score-only", dt)}
 
 
-GOLDEN = {"long_dna_local_262144": "long_local_262144.json", "long_dna_global_1k": "global_1k.json",
+GOLDEN = {"long_dna_local_262144": "long_local_262144.json", "long_dna_local_393216": "long_local_393216.json",
+          "long_dna_global_1k": "global_1k.json",
           "reads_semiglobal": "reads_sample.json", "protein_uneven": "protein_sample.json"}
 
 
@@ -373,7 +379,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="protein", choices=["long", "long_tb", "reads", "protein", "nw1k", "serve"])
+    ap.add_argument("--workload", default="protein", choices=["long", "long_tb", "long_tb_393216", "reads", "protein", "nw1k", "serve"])
     ap.add_argument("--no-serve", action="store_true", help="protein: leave out the serving record")
     ap.add_argument("--plain-pairs", type=int, default=2048, help="pairs timed one per call (the plain form)")
     ap.add_argument("--requests", type=int, default=200000, help="serve: number of requests")
@@ -398,6 +404,9 @@ def main():
     ap.add_argument("--no-compare", action="store_true",
                     help="batch workloads: skip the graph / per-length-bin / one-pair-per-call comparisons")
     ap.add_argument("--no-check", action="store_true")
+    ap.add_argument("--linear-space", action="store_true",
+                    help="long_tb: trace back in linear space (checkpoints, tiles relaxed again) even where the "
+                         "4-bit codes of every cell would fit")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the library has no multi-GPU path", file=sys.stderr)
@@ -436,6 +445,8 @@ def main():
     with torch.cuda.stream(stream):
         q, qo, s, so = aln.to_device(w)
         if long_path:
+            if args.linear_space:
+                flags |= aln.LINEAR_SPACE
             ba = aln.LongAligner(aln.scoring_of(w), q[:int(n[0])], s[:int(m[0])], flags)
         else:
             ba = aln.BatchAligner(aln.scoring_of(w), q, qo, s, so, int(n.max()), int(m.max()), flags)
@@ -509,7 +520,8 @@ def main():
         "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": dtype, "data": "synthetic (seeded generator, synth/__init__.py)",
         "config": {"workload": w.name, "pairs": w.n_pairs, "cells": cells, "mode": MODE_NAME[w.mode], "gap": gap,
-                   "gap_open": w.gap_open, "gap_extend": w.gap_extend, "traceback": bool(w.traceback)},
+                   "gap_open": w.gap_open, "gap_extend": w.gap_extend, "traceback": bool(w.traceback),
+                   "linear_space": bool(flags & aln.LINEAR_SPACE)},
         "parity": check,
         "roofline": roof,
     }

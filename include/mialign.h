@@ -234,19 +234,32 @@ aln_status_t aln_long_workspace_size(const aln_scoring_t* scoring, int64_t n, in
  * that move as a wavefront across the device (AnySeq Sec. IV-B: tiles relaxed along anti-diagonals,
  * each publishing its last row to the next), all bands drawn from one device-side work queue.
  *   q             DEVICE  n uint8 codes;  s  DEVICE  m uint8 codes
- *   flags         ALN_SCORE_ONLY, or ALN_TRACEBACK to also write the canonical CIGAR
+ *   flags         ALN_SCORE_ONLY, or ALN_TRACEBACK to also write the canonical CIGAR, optionally
+ *                 | ALN_LINEAR_SPACE
  *   out           DEVICE  one aln_result_t (q_begin = s_begin = -1 when score-only)
  *   cigar         DEVICE  CIGAR words, cigar_capacity of them (n + m always suffice); NULL when
  *                         score-only.  A short buffer gives ALN_RES_CIGAR_TRUNC and the required count.
  *   workspace     DEVICE  at least aln_long_workspace_size(...) bytes, 256-byte aligned: two bottom-row
- *                         slots of (m + 1) * 8 bytes, plus, with ALN_TRACEBACK, the 4-bit predecessor
- *                         code of every cell (about n * m / 2 bytes; the call returns ALN_E_UNSUPPORTED
- *                         above 64 GiB of codes).
+ *                         slots of (m + 1) * 8 bytes, plus, with ALN_TRACEBACK, either the 4-bit
+ *                         predecessor code of every cell (about n * m / 2 bytes, while that is at most
+ *                         64 GiB and ALN_LINEAR_SPACE is not given), or the linear-space traceback's
+ *                         checkpoints (the H and E of every 1024th row and the H and F of every 2048th
+ *                         column, about n * m / 85 bytes) and one segment of codes (aln_set_traceback_budget).
+ * Traceback in linear space (Sec. III-A): the forward pass keeps the checkpoints; the walk then goes back
+ * through segments of rows, bottom first, relaxing each segment's tiles again from the checkpoints (the
+ * same integers as the forward pass) and walking its codes.  At most twice the cells are relaxed.
  * Exactness: 32-bit lanes; the call returns ALN_E_SCORING if the score range of an n x m problem
  * could leave +-2^28. */
 aln_status_t aln_align_long(const aln_scoring_t* scoring, const uint8_t* q, int64_t n, const uint8_t* s, int64_t m,
                             uint32_t flags, aln_result_t* out, uint32_t* cigar, int64_t cigar_capacity,
                             void* workspace, size_t workspace_bytes, hipStream_t stream);
+
+/* Bytes of 4-bit predecessor codes a linear-space traceback (aln_align_long with ALN_LINEAR_SPACE, or
+ * above 64 GiB of codes) holds at once: the rows of a segment that the traceback relaxes again in one go
+ * are as many as fit (at least 1024).  A smaller budget means more segments, each relaxed and walked in
+ * turn.  0 restores the default of 4 GiB.  Process-wide; read when a size query or align call is made,
+ * so the same value must hold for both.  Returns ALN_E_INVALID for a negative size. */
+aln_status_t aln_set_traceback_budget(int64_t bytes);
 
 /* Kernel timing, a profiling aid.  While enabled, every kernel the library enqueues is bracketed by
  * HIP events recorded on the same stream; aln_profile_read waits for those events and returns, per

@@ -19,7 +19,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmialign.so")
 
 GLOBAL, LOCAL, SEMIGLOBAL = 0, 1, 2
-SCORE_ONLY, TRACEBACK, FORCE_INT32, FORCE_INT16 = 0, 1, 2, 4
+SCORE_ONLY, TRACEBACK, FORCE_INT32, FORCE_INT16, LINEAR_SPACE = 0, 1, 2, 4, 8
 RES_INT32_REDO, RES_CIGAR_TRUNC, RES_BAD_CODE, RES_TOO_LONG, RES_DEVICE_ERROR, RES_BAD_END = 1, 2, 4, 8, 16, 32
 CIGAR_M, CIGAR_I, CIGAR_D = 0, 1, 2
 
@@ -90,6 +90,7 @@ _SIGNATURES = {
     "aln_profile_reset": (ctypes.c_int32, []),
     "aln_profile_read": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
     "aln_set_wait_limits": (ctypes.c_int32, [ctypes.c_int64, ctypes.c_int64]),
+    "aln_set_traceback_budget": (ctypes.c_int32, [ctypes.c_int64]),
     "aln_traceback_workspace_size": (ctypes.c_int32, [ctypes.POINTER(aln_scoring_t), ctypes.c_int64, ctypes.c_int64,
                                                       ctypes.c_int64, ctypes.POINTER(ctypes.c_size_t)]),
     "aln_traceback": (ctypes.c_int32, [ctypes.POINTER(aln_scoring_t), ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
@@ -319,6 +320,13 @@ def aln_cigar_to_gapped(q: np.ndarray, s: np.ndarray, result, runs, letters: Opt
     if st != 0:
         raise AlnError(st, "aln_cigar_to_gapped")
     return qbuf.value.decode(), sbuf.value.decode()
+
+
+def aln_set_traceback_budget(nbytes: int = 0) -> None:
+    """Bytes of codes a linear-space traceback holds at once (0 = the library's default, 4 GiB)."""
+    st = lib().aln_set_traceback_budget(nbytes)
+    if st != 0:
+        raise AlnError(st, "aln_set_traceback_budget")
 
 
 def aln_set_wait_limits(device_polls: int = 0, lds_polls: int = 0) -> None:

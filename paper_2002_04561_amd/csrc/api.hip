@@ -339,6 +339,15 @@ static bool long_linear_space(int64_t n, int64_t m, uint32_t flags) {
 
 static const uint32_t kLongFlags = ALN_TRACEBACK | ALN_FORCE_INT32 | ALN_FORCE_INT16 | ALN_LINEAR_SPACE;
 
+// Bytes of predecessor codes a linear-space traceback holds at once (aln_set_traceback_budget).
+static int64_t g_ls_budget = kLsCodeBudget;
+
+aln_status_t aln_set_traceback_budget(int64_t bytes) {
+  if (bytes < 0) return ALN_E_INVALID;
+  g_ls_budget = bytes ? bytes : kLsCodeBudget;
+  return ALN_OK;
+}
+
 aln_status_t aln_long_workspace_size(const aln_scoring_t* scoring, int64_t n, int64_t m, uint32_t flags,
                                      size_t* bytes) {
   if (!bytes || n < 0 || m < 0 || n >= (1ll << 31) || m >= (1ll << 31)) return ALN_E_INVALID;
@@ -350,7 +359,7 @@ aln_status_t aln_long_workspace_size(const aln_scoring_t* scoring, int64_t n, in
   if (!fits_i32(kp, n, m)) return ALN_E_SCORING;
   if (long_linear_space(n, m, flags)) {
     LongLsPlan pl;
-    st = plan_long_ls(n, m, kLsCodeBudget, &pl);
+    st = plan_long_ls(n, m, g_ls_budget, &pl);
     if (st != ALN_OK) return st;
     *bytes = pl.total_bytes;
     return ALN_OK;
@@ -376,7 +385,7 @@ aln_status_t aln_align_long(const aln_scoring_t* scoring, const uint8_t* q, int6
   if (!fits_i32(kp, n, m)) return ALN_E_SCORING;
   if (long_linear_space(n, m, flags)) {
     LongLsPlan pl;
-    st = plan_long_ls(n, m, kLsCodeBudget, &pl);
+    st = plan_long_ls(n, m, g_ls_budget, &pl);
     if (st != ALN_OK) return st;
     if (!workspace || workspace_bytes < pl.total_bytes) return ALN_E_WORKSPACE;
     return launch_long_ls(kp, pl, q, n, s, m, out, cigar, cigar_capacity, workspace, stream);

@@ -8,20 +8,21 @@ device memory they need stays within the budget; a request that does not fit wai
 be released by finishing batches.  Sequences are copied once into device memory at admission and
 stay there until their batch completes.
 
-Memory a request holds while admitted (bytes):
-    sequences n + m, offsets and result 48, CIGAR 4 (n + m) when traced back, plus the DP/traceback
-    state of its path: a wavefront pair keeps two rows of (m + 1) x 8 bytes (and n*m/2 bytes of
-    predecessor codes when traced back); a pair of a batch shares the batch kernel's per-wave row
-    buffers, counted as 8 (m + 1) bytes per pair, and with traceback its predecessor codes n*m/2.
+Memory a batch holds while in flight is what its calls allocate on the device: the workspace the
+library's size query asks for (aln_batch_workspace_size, or aln_long_workspace_size for a request that
+runs alone), plus the sequences, offsets, results and CIGAR buffers, each rounded up to the caching
+allocator's 512-byte blocks (`AlignServer.batch_bytes`).  Admission takes the longest FIFO prefix of
+a class whose batch fits what the budget has left.
 
-The admission logic (`Admission`) is plain Python so it can be exercised without a device.
+The admission logic (`Admission`) is plain Python with the cost of a batch passed in, so it can be
+exercised without a device; `request_bytes` is the stand-alone estimate it uses when no cost is given.
 """
 from __future__ import annotations
 
 import collections
 import time
 from dataclasses import dataclass, field
-from typing import Dict, List, Optional
+from typing import Callable, Dict, List, Optional
 
 import numpy as np
 
@@ -38,6 +39,8 @@ class Request:
 
 
 def request_bytes(r: Request) -> int:
+    """A device-free estimate of one request's memory: sequences, offsets and result, CIGAR room, two DP
+    rows, and the 4-bit codes of every cell when traced back."""
     n, m = len(r.q), len(r.s)
     b = n + m + 48
     if r.traceback:
@@ -46,18 +49,60 @@ def request_bytes(r: Request) -> int:
     return b
 
 
-class Admission:
-    """FIFO-per-class admission against a byte budget.  Pure bookkeeping, no device."""
+@dataclass
+class BatchShape:
+    """What the memory of a batch of one class depends on."""
+    klass: str
+    n_pairs: int
+    total_q: int
+    total_s: int
+    max_n: int
+    max_m: int
+    cells: int  # sum of n * m
+    traceback: bool
+    long: bool
 
-    def __init__(self, budget_bytes: int):
+
+def estimate_bytes(b: BatchShape) -> int:
+    """The sum of request_bytes over the batch's requests."""
+    x = b.total_q + b.total_s + 48 * b.n_pairs + (16 if b.long else 8) * (b.total_s + b.n_pairs)
+    if b.traceback:
+        x += 4 * (b.total_q + b.total_s) + (b.cells + b.n_pairs) // 2
+    return x
+
+
+class Admission:
+    """FIFO-per-class admission against a byte budget.  Pure bookkeeping, no device.
+
+    cost(shape) gives the bytes a batch of that shape (all of one class) holds on the device; it must not
+    shrink when a request is added.  The default, estimate_bytes, sums request_bytes."""
+
+    def __init__(self, budget_bytes: int, cost: Optional[Callable[[BatchShape], int]] = None):
         self.budget = int(budget_bytes)
+        self.cost = cost or estimate_bytes
         self.in_use = 0
         self.peak = 0
         self.waiting: Dict[str, collections.deque] = collections.defaultdict(collections.deque)
+        self.charged: Dict[int, int] = {}  # id(batch) -> bytes charged
+
+    @staticmethod
+    def shapes(reqs: List[Request]):
+        """shape(k): the BatchShape of the first k requests (prefix sums and maxima computed once)."""
+        n = np.fromiter((len(r.q) for r in reqs), np.int64, len(reqs))
+        m = np.fromiter((len(r.s) for r in reqs), np.int64, len(reqs))
+        cq, cs, cc = np.cumsum(n), np.cumsum(m), np.cumsum(n * m)
+        mn, mm = np.maximum.accumulate(n), np.maximum.accumulate(m)
+        r0 = reqs[0]
+
+        def shape(k: int) -> BatchShape:
+            return BatchShape(r0.klass, k, int(cq[k - 1]), int(cs[k - 1]), int(mn[k - 1]), int(mm[k - 1]),
+                              int(cc[k - 1]), r0.traceback, r0.long)
+        return shape
 
     def arrive(self, r: Request):
-        if request_bytes(r) > self.budget:
-            raise ValueError("request %d needs %d bytes, more than the whole budget" % (r.rid, request_bytes(r)))
+        need = self.cost(self.shapes([r])(1))
+        if need > self.budget:
+            raise ValueError("request %d needs %d bytes, more than the whole budget" % (r.rid, need))
         self.waiting[r.klass].append(r)
 
     def oldest_class(self, exclude=()) -> Optional[str]:
@@ -70,27 +115,39 @@ class Admission:
         return best
 
     def take_batch(self, klass: str, max_pairs: int) -> List[Request]:
-        """Admits the longest FIFO prefix of `klass` that fits the budget (a long request goes alone)."""
+        """Admits the longest FIFO prefix of `klass` whose batch fits what the budget has left (a long
+        request goes alone).  The prefix length is found by bisection, the cost being monotone in it."""
         dq = self.waiting[klass]
-        out: List[Request] = []
-        while dq and len(out) < max_pairs:
-            r = dq[0]
-            need = request_bytes(r)
-            if self.in_use + need > self.budget:
-                break
-            if r.long and out:
-                break
-            dq.popleft()
-            self.in_use += need
-            self.peak = max(self.peak, self.in_use)
-            out.append(r)
-            if r.long:
-                break
+        if not dq:
+            return []
+        room = self.budget - self.in_use
+        if dq[0].long:
+            cand = [dq[0]]
+        else:
+            cand = []
+            for r in dq:
+                if r.long or len(cand) >= max_pairs:
+                    break
+                cand.append(r)
+        shape = self.shapes(cand)
+        lo, hi = 0, len(cand)  # the largest k whose batch fits the room left
+        while lo < hi:
+            mid = (lo + hi + 1) // 2
+            if self.cost(shape(mid)) <= room:
+                lo = mid
+            else:
+                hi = mid - 1
+        if lo == 0:
+            return []
+        out = [dq.popleft() for _ in range(lo)]
+        need = self.cost(shape(lo))
+        self.in_use += need
+        self.peak = max(self.peak, self.in_use)
+        self.charged[id(out)] = need
         return out
 
     def release(self, batch: List[Request]):
-        for r in batch:
-            self.in_use -= request_bytes(r)
+        self.in_use -= self.charged.pop(id(batch))
         assert self.in_use >= 0
 
     def pending(self) -> int:
@@ -128,7 +185,7 @@ class AlignServer:
         import paper_2002_04561_amd as aln
         self.torch, self.aln = torch, aln
         self.scorings = scorings
-        self.adm = Admission(budget_bytes)
+        self.adm = Admission(budget_bytes, self.batch_bytes)
         self.streams = [torch.cuda.Stream(device=device) for _ in range(streams)]
         self.max_pairs = max_pairs
         self.class_max_pairs = dict(class_max_pairs or {})
@@ -138,6 +195,23 @@ class AlignServer:
         self.completed: List[Completed] = []
         self.cells = 0
         self.redo = 0  # requests whose 16-bit pass was redone in 32 bits
+
+    def batch_bytes(self, b: BatchShape) -> int:
+        """Device bytes a batch allocates while in flight: the library's workspace for it (its size query)
+        and the buffers _launch creates, each rounded up to the allocator's 512-byte blocks."""
+        aln = self.aln
+        blk = lambda x: (max(int(x), 1) + 511) // 512 * 512  # noqa: E731
+        sc = self.scorings[b.klass]
+        flags = aln.TRACEBACK if b.traceback else aln.SCORE_ONLY
+        if b.long:
+            ws = aln.aln_long_workspace_size(sc, b.total_q, b.total_s, flags)
+            x = blk(max(ws, 256)) + blk(b.total_q) + blk(b.total_s) + blk(32)
+            return x + (blk(4 * (b.total_q + b.total_s + 1)) if b.traceback else 0)
+        ws = aln.aln_batch_workspace_size(sc, b.n_pairs, b.max_n, b.max_m, b.total_q, b.total_s, flags)
+        x = blk(max(ws, 256)) + blk(b.total_q) + blk(b.total_s) + 2 * blk(8 * (b.n_pairs + 1)) + blk(32 * b.n_pairs)
+        if b.traceback:
+            x += blk(4 * (b.total_q + b.total_s + b.n_pairs)) + blk(8 * (b.n_pairs + 1))
+        return x
 
     def _launch(self, batch: List[Request], stream) -> _Flight:
         torch, aln = self.torch, self.aln

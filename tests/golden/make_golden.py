@@ -32,6 +32,18 @@ def long_local_262144():
             "oracle_seconds": round(time.time() - t0, 1)}
 
 
+def long_local_393216():
+    """The 393216 x 393216 local affine DNA pair (score and end cell): its 4-bit codes would take 72 GiB, so
+    its traceback runs in linear space."""
+    w = synth.long_dna_local(seed=2, n=393216)
+    a, b = w.pair(0)
+    t0 = time.time()
+    r = oracle.align(_sc(w), a, b, impl="linspace")
+    return {"workload": "long_dna_local(seed=2, n=393216)", "mode": "local", "gap_open": -3, "gap_extend": -1,
+            "match": 2, "mismatch": -3, "score": r.score, "q_end": r.q_end, "s_end": r.s_end,
+            "oracle_seconds": round(time.time() - t0, 1)}
+
+
 def global_1k():
     """The 1000 x 1000 global linear DNA pair with its canonical CIGAR."""
     w = synth.long_dna_global_1k(seed=1)
@@ -119,7 +131,7 @@ def serve_sample():
     return out
 
 
-JOBS = {"long_local_262144": long_local_262144, "global_1k": global_1k, "reads_sample": reads_sample,
+JOBS = {"long_local_262144": long_local_262144, "long_local_393216": long_local_393216, "global_1k": global_1k, "reads_sample": reads_sample,
         "protein_sample": protein_sample, "reads_digest": reads_digest, "protein_digest": protein_digest,
         "serve_sample": serve_sample}
 

@@ -82,10 +82,10 @@ def test_batch_config_validation_on_host():
 
 
 def test_long_size_query_host_checks():
-    """aln_long_workspace_size refuses, before any device query, a traceback whose 4-bit codes would exceed
-    64 GiB (ALN_E_UNSUPPORTED), a score range beyond exact 32-bit lanes (ALN_E_SCORING), an invalid mode
-    and a negative length (ALN_E_INVALID)."""
-    cases = [(aln.Scoring(1, 4, -3, -1, 2, -3), 400000, 400000, aln.TRACEBACK, -6),
+    """aln_long_workspace_size refuses, before any device query, an unknown flag, a score range beyond exact
+    32-bit lanes (ALN_E_SCORING), an invalid mode and a negative length (ALN_E_INVALID).  A traceback
+    above 64 GiB of codes is no longer refused: it runs in linear space."""
+    cases = [(aln.Scoring(1, 4, -3, -1, 2, -3), 400000, 400000, aln.TRACEBACK | 16, -1),
              (aln.Scoring(1, 4, -3, -1, 100, -3), 3000000, 3000000, 0, -3),
              (aln.Scoring(5, 4, -3, -1, 2, -3), 10, 10, 0, -1),
              (aln.Scoring(1, 4, -3, -1, 2, -3), -1, 10, 0, -1)]
@@ -101,3 +101,8 @@ def test_wait_limits_host_checks():
     assert aln.lib().aln_set_wait_limits(-1, 0) == -1
     assert aln.lib().aln_set_wait_limits(0, -5) == -1
     assert aln.lib().aln_set_wait_limits(0, 0) == 0
+
+
+def test_traceback_budget_host_checks():
+    assert aln.lib().aln_set_traceback_budget(-1) == -1
+    assert aln.lib().aln_set_traceback_budget(0) == 0

@@ -57,14 +57,24 @@ def _alone(reqs, scorings):
 
 
 def test_mix_equals_oracle_and_alone_and_budget(gpu):
+    """Every served result equals the oracle's and its result alone; the device memory the server's batches
+    held at once (torch's allocator peak over the run) stays within the budget."""
+    import torch
+
     from paper_2002_04561_amd.serve import AlignServer
     reqs, items, sig = _stream(21, 400, 20000.0)
     sc = _scorings(sig)
-    budget = 64 << 20
+    budget = 256 << 20
     srv = AlignServer(sc, budget_bytes=budget, streams=3, max_pairs=64)
+    torch.cuda.synchronize()
+    base = torch.cuda.memory_allocated()
+    torch.cuda.reset_peak_memory_stats()
     stats = srv.run(reqs, realtime=True)
+    torch.cuda.synchronize()
+    live_peak = torch.cuda.max_memory_allocated() - base
     assert stats["requests"] == len(reqs)
     assert stats["peak_bytes"] <= budget
+    assert live_peak <= budget, (live_peak, budget)
     got = {c.rid: (c.result, c.cigar) for c in srv.completed}
     assert sorted(got) == sorted(r.rid for r in reqs)
     expect = _oracle_results(items, sig)
@@ -77,13 +87,23 @@ def test_mix_equals_oracle_and_alone_and_budget(gpu):
 
 
 def test_tiny_budget_completes(gpu):
-    from paper_2002_04561_amd.serve import AlignServer, request_bytes
+    """A budget that holds only the largest single request's batch: requests go one or a few at a time,
+    all complete, and the allocator's peak stays within the budget."""
+    import torch
+
+    from paper_2002_04561_amd.serve import Admission, AlignServer
     reqs, items, sig = _stream(22, 60, 50000.0)
     reqs = [r for r in reqs if not r.long]
-    budget = max(request_bytes(r) for r in reqs) + 1
+    srv = AlignServer(_scorings(sig), budget_bytes=1 << 40, streams=2, max_pairs=64)
+    budget = max(srv.batch_bytes(Admission.shapes([r])(1)) for r in reqs) + 1
     srv = AlignServer(_scorings(sig), budget_bytes=budget, streams=2, max_pairs=64)
+    torch.cuda.synchronize()
+    base = torch.cuda.memory_allocated()
+    torch.cuda.reset_peak_memory_stats()
     stats = srv.run(reqs, realtime=False)
+    torch.cuda.synchronize()
     assert stats["requests"] == len(reqs) and stats["peak_bytes"] <= budget
+    assert torch.cuda.max_memory_allocated() - base <= budget
     expect = _oracle_results([it for it in items if it.klass != "long"], sig)
     bad = [c.rid for c in srv.completed if (c.result, c.cigar) != expect[c.rid]]
     assert not bad, bad[:10]

@@ -112,3 +112,33 @@ def test_in_place_and_bad_end_cells(gpu):
         exp = (int(ores["score"][k]), int(ores["q_begin"][k]), int(ores["q_end"][k]), int(ores["s_begin"][k]),
                int(ores["s_end"][k]), 0, ocig[k])
         assert got == exp, k
+
+
+def test_mixed_length_traceback_batch(gpu):
+    """A traceback batch whose lengths spread log-uniformly over 64..4096 (local affine protein table): every
+    pair's CIGAR equals the oracle's, through aln_align_batch with ALN_TRACEBACK and through a score-only
+    call followed by aln_traceback.  The traceback slabs of the one-pair-per-lane kernels run fewer waves
+    when the largest pair would make them exceed their budget, so the workspace stays bounded."""
+    import torch
+
+    import paper_2002_04561_amd as aln
+    rng = np.random.default_rng(17)
+    sig = synth.protein_sigma(rng)
+    lens = np.rint(np.exp(rng.uniform(np.log(64), np.log(4096), (96, 2)))).astype(int)
+    qs = [rng.integers(0, 20, n, dtype=np.uint8) for n, _ in lens]
+    ss = [rng.integers(0, 20, m, dtype=np.uint8) for _, m in lens]
+    q, qo = synth.pack(qs)
+    s, so = synth.pack(ss)
+    w = synth.Workload("mixed_tb", synth.LOCAL, 20, -11, -1, q, qo, s, so, subst=sig, traceback=True)
+    ores, ocig = run_oracle(w, True)
+    ba, (dq, dqo, ds, dso) = _forward(w, aln.TRACEBACK)
+    assert ba.ws_bytes < (9 << 30)
+    res = ba.results()
+    bad = compare(w, res, ba.cigars(), ores, ocig, "batch")
+    assert not bad, bad[:3]
+    fw, _ = _forward(w, aln.SCORE_ONLY)
+    n, m = w.lengths()
+    tres, truns = aln.traceback_pairs(aln.scoring_of(w), dq, dqo, ds, dso, int(n.max()), int(m.max()), fw.out)
+    bad = compare(w, tres, truns, ores, ocig, "traceback")
+    assert not bad, bad[:3]
+    torch.cuda.synchronize()

@@ -68,3 +68,29 @@ def test_oldest_class_skips_excluded_classes():
     assert adm.oldest_class(exclude={"long"}) == "read"
     assert adm.oldest_class(exclude={"long", "read"}) == "protein"
     assert adm.oldest_class(exclude={"long", "read", "protein"}) is None
+
+
+def test_longest_prefix_under_a_given_cost():
+    """With a cost passed in, a batch is the longest FIFO prefix whose cost fits what is left, found by
+    bisection; the charge is the cost of the batch taken, and release returns exactly that."""
+    from paper_2002_04561_amd.serve import BatchShape
+    calls = []
+
+    def cost(b: BatchShape) -> int:
+        calls.append(b.n_pairs)
+        return 1000 + 10 * b.total_q + b.max_m  # grows with every added request
+    reqs = [_req(k, "a", 10 + k, 20, k * 1e-3) for k in range(100)]
+    adm = Admission(5000, cost)
+    for r in reqs:
+        adm.arrive(r)
+    calls.clear()
+    first = adm.take_batch("a", 64)
+    assert len(calls) < 10  # bisection, not one call per request
+    k = len(first)
+    tq = sum(10 + j for j in range(k))
+    assert cost(BatchShape("a", k, tq, 20 * k, 9 + k, 20, 0, False, False)) <= 5000
+    tq2 = tq + 10 + k
+    assert 1000 + 10 * tq2 + 20 > 5000  # one more would not fit
+    assert adm.in_use == 1000 + 10 * tq + 20
+    adm.release(first)
+    assert adm.in_use == 0
