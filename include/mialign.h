@@ -185,6 +185,23 @@ aln_status_t aln_align_batch_ex(const aln_scoring_t* scoring, int64_t n_pairs, c
                                 const int64_t* cigar_off, void* workspace, size_t workspace_bytes,
                                 hipStream_t stream);
 
+/* aln_align_batch_ex for callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, hosts that forbid allocation): the same arguments without a workspace, whose place
+ * takes a device scratch array the library holds on each device for the life of the process
+ * (aln_noalloc_scratch_bytes(), 64 MiB).  Nothing is allocated: the scratch's device address is looked up
+ * once per device.  Returns ALN_E_WORKSPACE, with no device work, when the batch needs more than the
+ * scratch (aln_batch_workspace_size); otherwise as aln_align_batch_ex.  Every call on a device shares
+ * that device's scratch: calls that overlap on one device (on different streams, or from different
+ * threads) race and must not be made. */
+aln_status_t aln_align_batch_noalloc(const aln_scoring_t* scoring, int64_t n_pairs, const uint8_t* q,
+                                     const int64_t* q_off, const uint8_t* s, const int64_t* s_off, int64_t max_n,
+                                     int64_t max_m, int64_t total_q, int64_t total_s, uint32_t flags,
+                                     const aln_batch_config_t* config, aln_result_t* out, uint32_t* cigar,
+                                     const int64_t* cigar_off, hipStream_t stream);
+
+/* Bytes of the device scratch of aln_align_batch_noalloc. */
+size_t aln_noalloc_scratch_bytes(void);
+
 /* Bytes of device workspace aln_traceback needs for n_pairs pairs whose lengths are at most max_n and
  * max_m.  Returns ALN_OK and sets *bytes. */
 aln_status_t aln_traceback_workspace_size(const aln_scoring_t* scoring, int64_t n_pairs, int64_t max_n,

@@ -90,6 +90,12 @@ _SIGNATURES = {
     "aln_profile_reset": (ctypes.c_int32, []),
     "aln_profile_read": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
     "aln_set_wait_limits": (ctypes.c_int32, [ctypes.c_int64, ctypes.c_int64]),
+    "aln_align_batch_noalloc": (ctypes.c_int32, [ctypes.POINTER(aln_scoring_t), ctypes.c_int64, ctypes.c_void_p,
+                                                 ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                                 ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, ctypes.c_uint32,
+                                                 ctypes.POINTER(aln_batch_config_t), ctypes.c_void_p,
+                                                 ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "aln_noalloc_scratch_bytes": (ctypes.c_size_t, []),
     "aln_set_traceback_budget": (ctypes.c_int32, [ctypes.c_int64]),
     "aln_traceback_workspace_size": (ctypes.c_int32, [ctypes.POINTER(aln_scoring_t), ctypes.c_int64, ctypes.c_int64,
                                                       ctypes.c_int64, ctypes.POINTER(ctypes.c_size_t)]),

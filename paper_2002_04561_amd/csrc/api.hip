@@ -1,5 +1,6 @@
 // C-ABI entry points of mialign: argument validation, workspace sizing and dispatch.
 #include <cstring>
+#include <mutex>
 
 #include "internal.h"
 
@@ -252,6 +253,49 @@ aln_status_t aln_align_batch_ex(const aln_scoring_t* scoring, int64_t n_pairs, c
   return launch_batch_i32(kp, L.bp, q, q_off, s, s_off, tb, out, cigar, cigar_off, workspace, redo_idx, redo_cnt,
                           ALN_RES_INT32_REDO, ticket32, stream);
 }
+
+// Device scratch of aln_align_batch_noalloc: the workspace of calls that cannot allocate.  Each device the
+// library runs on holds its own copy for the life of the process.  In host code `scratch` names a host-side
+// stand-in, never the device memory: the device address is taken once per device with hipGetSymbolAddress
+// and kept in g_scratch_ptr, and only that address is handed to kernels.
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices] = {};
+
+static aln_status_t scratch_address(void** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return ALN_E_DEVICE;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return ALN_E_DEVICE;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return ALN_OK;
+}
+
+aln_status_t aln_align_batch_noalloc(const aln_scoring_t* scoring, int64_t n_pairs, const uint8_t* q,
+                                     const int64_t* q_off, const uint8_t* s, const int64_t* s_off, int64_t max_n,
+                                     int64_t max_m, int64_t total_q, int64_t total_s, uint32_t flags,
+                                     const aln_batch_config_t* config, aln_result_t* out, uint32_t* cigar,
+                                     const int64_t* cigar_off, hipStream_t stream) {
+  size_t need = 0;
+  aln_status_t st = aln_batch_workspace_size(scoring, n_pairs, max_n, max_m, total_q, total_s, flags, &need);
+  if (st != ALN_OK) return st;
+  if (need > kScratchBytes) return ALN_E_WORKSPACE;
+  void* ws = nullptr;
+  st = scratch_address(&ws);
+  if (st != ALN_OK) return st;
+  // the batch path clears every counter and ticket it uses with small kernels, so the scratch's
+  // contents from an earlier call do not matter
+  return aln_align_batch_ex(scoring, n_pairs, q, q_off, s, s_off, max_n, max_m, total_q, total_s, flags, config, out,
+                            cigar, cigar_off, ws, kScratchBytes, stream);
+}
+
+size_t aln_noalloc_scratch_bytes(void) { return kScratchBytes; }
 
 // aln_traceback: the 32-bit one-pair-per-lane slabs, then the group ticket.
 static aln_status_t tb_layout(const KParams& kp, int64_t n_pairs, int64_t max_n, int64_t max_m, BatchPlan* bp,
