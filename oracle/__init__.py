@@ -85,6 +85,10 @@ def _load():
                 f.argtypes = [ctypes.POINTER(_Scoring), u8p, ctypes.c_int64, u8p, ctypes.c_int64, ctypes.c_int,
                               ctypes.POINTER(_Result), u32p, ctypes.c_int64]
                 f.restype = ctypes.c_int
+            f = lib.orc_align_affine_checkpointed
+            f.argtypes = [ctypes.POINTER(_Scoring), u8p, ctypes.c_int64, u8p, ctypes.c_int64, ctypes.c_int64,
+                          ctypes.POINTER(_Result), u32p, ctypes.c_int64]
+            f.restype = ctypes.c_int
             f = lib.orc_score_affine_linear_space
             f.argtypes = [ctypes.POINTER(_Scoring), u8p, ctypes.c_int64, u8p, ctypes.c_int64, ctypes.POINTER(_Result)]
             f.restype = ctypes.c_int
@@ -148,9 +152,11 @@ def _ptr(a: np.ndarray, ct):
     return a.ctypes.data_as(ctypes.POINTER(ct))
 
 
-def align(sc: Scoring, q: Sequence[int], s: Sequence[int], traceback: bool = False, impl: str = "affine") -> Alignment:
-    """One pair.  impl: 'affine' (full H/E/F), 'linear' (one-matrix Eqs. (2)-(3), needs gap_open == 0)
-    or 'linspace' (score-only, two rows)."""
+def align(sc: Scoring, q: Sequence[int], s: Sequence[int], traceback: bool = False, impl: str = "affine",
+          block_rows: int = 512) -> Alignment:
+    """One pair.  impl: 'affine' (full H/E/F), 'linear' (one-matrix Eqs. (2)-(3), needs gap_open == 0),
+    'linspace' (score-only, two rows) or 'checkpointed' (the affine results with the traceback in linear
+    space: every block_rows-th row kept, one block recomputed at a time)."""
     lib = _load()
     qa, sa = _u8(q), _u8(s)
     n, m = len(qa), len(sa)
@@ -165,6 +171,11 @@ def align(sc: Scoring, q: Sequence[int], s: Sequence[int], traceback: bool = Fal
     elif impl == "linear":
         rc = lib.orc_align_linear_full(ctypes.byref(sc.c()), qp, n, sp, m, int(traceback), ctypes.byref(res),
                                        _ptr(cig, ctypes.c_uint32), cap)
+    elif impl == "checkpointed":
+        if not traceback:
+            raise ValueError("checkpointed is the traceback")
+        rc = lib.orc_align_affine_checkpointed(ctypes.byref(sc.c()), qp, n, sp, m, int(block_rows), ctypes.byref(res),
+                                               _ptr(cig, ctypes.c_uint32), cap)
     elif impl == "linspace":
         if traceback:
             raise ValueError("linspace is score-only")

@@ -226,6 +226,192 @@ int orc_align_affine_full(const orc_scoring* sc, const uint8_t* q, int64_t n, co
 }
 
 /* ---------------------------------------------------------------------- */
+/* The same alignment in linear space (Sec. III-A: the traceback can run in */
+/* linear space at the cost of recomputing the matrix).  The forward pass   */
+/* keeps two rows, finds the optimum by the same row-major scan as above,   */
+/* and keeps the H and E of every block_rows-th row.  The walk then goes    */
+/* back block by block: the block holding the walk's row is recomputed from */
+/* the kept row above it, as full H/E/F matrices up to the walk's cell, and */
+/* the walk takes exactly the steps of orc_align_affine_full until it       */
+/* reaches the block's first row, where the block above takes over.        */
+/* ---------------------------------------------------------------------- */
+int orc_align_affine_checkpointed(const orc_scoring* sc, const uint8_t* q, int64_t n, const uint8_t* s, int64_t m,
+                                  int64_t block_rows, orc_result* res, uint32_t* cigar, int64_t cigar_cap) {
+  const int64_t go = sc->gap_open, ge = sc->gap_extend;
+  const int32_t A = sc->alphabet_size;
+  const int64_t K = block_rows;
+  memset(res, 0, sizeof(*res));
+  res->q_begin = res->s_begin = -1;
+  if (K < 1) return -2;
+  if (!check_codes(q, n, A) || !check_codes(s, m, A)) {
+    res->flags = ORC_BAD_CODE;
+    return 0;
+  }
+  const int64_t W = m + 1;
+  const int64_t nck = n / K + 1; /* kept rows 0, K, 2K, ... */
+  int64_t* ckH = (int64_t*)malloc(sizeof(int64_t) * nck * W);
+  int64_t* ckE = (int64_t*)malloc(sizeof(int64_t) * nck * W);
+  int64_t* pH = (int64_t*)malloc(sizeof(int64_t) * W);
+  int64_t* pE = (int64_t*)malloc(sizeof(int64_t) * W);
+  int64_t* cH = (int64_t*)malloc(sizeof(int64_t) * W);
+  int64_t* cE = (int64_t*)malloc(sizeof(int64_t) * W);
+  const int64_t rows_b = (K < n ? K : n) + 1;
+  int64_t* Hm = (int64_t*)malloc(sizeof(int64_t) * rows_b * W);
+  int64_t* Em = (int64_t*)malloc(sizeof(int64_t) * rows_b * W);
+  int64_t* Fm = (int64_t*)malloc(sizeof(int64_t) * rows_b * W);
+  uint8_t* ops = (uint8_t*)malloc((size_t)(n + m + 1));
+  if (!ckH || !ckE || !pH || !pE || !cH || !cE || !Hm || !Em || !Fm || !ops) {
+    free(ckH), free(ckE), free(pH), free(pE), free(cH), free(cE), free(Hm), free(Em), free(Fm), free(ops);
+    return -1;
+  }
+  /* forward pass; the optimum scan visits the cells in the order of orc_align_affine_full's */
+  int64_t bi = n, bj = m, best = 0;
+  int first = 1;
+  for (int64_t i = 0; i <= n; ++i) {
+    if (i == 0) {
+      for (int64_t j = 0; j <= m; ++j) {
+        cH[j] = (sc->mode == ORC_GLOBAL && j > 0) ? go + j * ge : 0;
+        cE[j] = NEG;
+      }
+    } else {
+      int64_t fl = NEG; /* F(i, j - 1) */
+      cH[0] = (sc->mode == ORC_GLOBAL) ? go + i * ge : 0;
+      cE[0] = NEG;
+      for (int64_t j = 1; j <= m; ++j) {
+        int64_t e = max2(pE[j] + ge, pH[j] + go + ge);
+        int64_t f = max2(fl + ge, cH[j - 1] + go + ge);
+        int64_t d = pH[j - 1] + sc->sigma[q[i - 1] * A + s[j - 1]];
+        int64_t h = max2(max2(d, e), f);
+        if (sc->mode == ORC_LOCAL) h = max2(h, 0);
+        cE[j] = e;
+        fl = f;
+        cH[j] = h;
+      }
+    }
+    for (int64_t j = 0; j <= m; ++j) {
+      if (sc->mode == ORC_LOCAL) {
+        if (i == 0 && j == 0) {
+          best = cH[0];
+          bi = 0;
+          bj = 0;
+        } else if (cH[j] > best) {
+          best = cH[j];
+          bi = i;
+          bj = j;
+        }
+      } else if (sc->mode == ORC_SEMIGLOBAL) {
+        if (i != n && j != m) continue;
+        if (first || cH[j] > best) {
+          best = cH[j];
+          bi = i;
+          bj = j;
+          first = 0;
+        }
+      }
+    }
+    if (sc->mode == ORC_GLOBAL && i == n) best = cH[m];
+    if (i % K == 0) {
+      memcpy(ckH + (i / K) * W, cH, sizeof(int64_t) * W);
+      memcpy(ckE + (i / K) * W, cE, sizeof(int64_t) * W);
+    }
+    int64_t* t = pH;
+    pH = cH;
+    cH = t;
+    t = pE;
+    pE = cE;
+    cE = t;
+  }
+  res->score = best;
+  res->q_end = bi;
+  res->s_end = bj;
+  /* the walk, block by block */
+  int64_t n_ops = 0, i = bi, j = bj;
+  int state = 0; /* 0 = H, 1 = E, 2 = F */
+  for (;;) {
+    /* the borders, as in orc_align_affine_full (local walks stop there too: H is 0) */
+    if (state == 0 && (i == 0 || j == 0)) {
+      if (sc->mode == ORC_GLOBAL) {
+        while (j > 0) {
+          ops[n_ops++] = ORC_OP_D;
+          --j;
+        }
+        while (i > 0) {
+          ops[n_ops++] = ORC_OP_I;
+          --i;
+        }
+      }
+      break;
+    }
+    /* recompute the block of row i: rows r0 .. i, columns 0 .. j */
+    const int64_t b = (i - 1) / K, r0 = b * K;
+#define BH(r, c) Hm[((r) - r0) * W + (c)]
+#define BE(r, c) Em[((r) - r0) * W + (c)]
+#define BF(r, c) Fm[((r) - r0) * W + (c)]
+    for (int64_t c = 0; c <= j; ++c) {
+      BH(r0, c) = ckH[b * W + c];
+      BE(r0, c) = ckE[b * W + c];
+      BF(r0, c) = NEG; /* never read: the walk leaves the block before a step on row r0 */
+    }
+    for (int64_t r = r0 + 1; r <= i; ++r) {
+      BH(r, 0) = (sc->mode == ORC_GLOBAL) ? go + r * ge : 0;
+      BE(r, 0) = NEG;
+      BF(r, 0) = NEG;
+      for (int64_t c = 1; c <= j; ++c) {
+        int64_t e = max2(BE(r - 1, c) + ge, BH(r - 1, c) + go + ge);
+        int64_t f = max2(BF(r, c - 1) + ge, BH(r, c - 1) + go + ge);
+        int64_t d = BH(r - 1, c - 1) + sc->sigma[q[r - 1] * A + s[c - 1]];
+        int64_t h = max2(max2(d, e), f);
+        if (sc->mode == ORC_LOCAL) h = max2(h, 0);
+        BE(r, c) = e;
+        BF(r, c) = f;
+        BH(r, c) = h;
+      }
+    }
+    /* the steps of orc_align_affine_full, inside the block */
+    int done = 0;
+    for (;;) {
+      if (state != 2 && i == r0 && r0 > 0) break; /* the block above holds the next step */
+      if (state == 0) {
+        if (i == 0 || j == 0) break;                     /* the borders, above */
+        if (sc->mode == ORC_LOCAL && BH(i, j) == 0) {
+          done = 1;
+          break;
+        }
+        int64_t d = BH(i - 1, j - 1) + sc->sigma[q[i - 1] * A + s[j - 1]];
+        if (d == BH(i, j)) {
+          ops[n_ops++] = ORC_OP_M;
+          --i;
+          --j;
+        } else if (BE(i, j) == BH(i, j)) {
+          state = 1;
+        } else {
+          state = 2;
+        }
+      } else if (state == 1) {
+        ops[n_ops++] = ORC_OP_I;
+        if (BH(i - 1, j) + go + ge == BE(i, j)) state = 0;
+        --i;
+      } else {
+        ops[n_ops++] = ORC_OP_D;
+        if (BH(i, j - 1) + go + ge == BF(i, j)) state = 0;
+        --j;
+      }
+    }
+#undef BH
+#undef BE
+#undef BF
+    if (done) break;
+  }
+  res->q_begin = i;
+  res->s_begin = j;
+  int trunc = 0;
+  res->cigar_len = emit_cigar(ops, n_ops, cigar, cigar_cap, &trunc);
+  if (trunc) res->flags |= ORC_CIGAR_TRUNC;
+  free(ckH), free(ckE), free(pH), free(pE), free(cH), free(cE), free(Hm), free(Em), free(Fm), free(ops);
+  return 0;
+}
+
+/* ---------------------------------------------------------------------- */
 /* Linear gap, Eqs. (2)-(3): one matrix H; priority diag > up (I) > left.  */
 /* ---------------------------------------------------------------------- */
 int orc_align_linear_full(const orc_scoring* sc, const uint8_t* q, int64_t n, const uint8_t* s, int64_t m,

@@ -35,6 +35,11 @@ typedef struct {
 /* Full H/E/F matrices in int64; traceback when want_cigar.  Returns 0, or -1 on allocation failure. */
 int orc_align_affine_full(const orc_scoring* sc, const uint8_t* q, int64_t n, const uint8_t* s, int64_t m,
                           int want_cigar, orc_result* res, uint32_t* cigar, int64_t cigar_cap);
+/* The same results as orc_align_affine_full with a traceback, in linear space: every block_rows-th row of
+ * H and E kept by the forward pass, one block of full matrices recomputed at a time for the walk.
+ * Returns 0, -1 on allocation failure, -2 for block_rows < 1. */
+int orc_align_affine_checkpointed(const orc_scoring* sc, const uint8_t* q, int64_t n, const uint8_t* s, int64_t m,
+                                  int64_t block_rows, orc_result* res, uint32_t* cigar, int64_t cigar_cap);
 /* One-matrix linear-gap DP (requires gap_open == 0, else returns -2). */
 int orc_align_linear_full(const orc_scoring* sc, const uint8_t* q, int64_t n, const uint8_t* s, int64_t m,
                           int want_cigar, orc_result* res, uint32_t* cigar, int64_t cigar_cap);

@@ -44,6 +44,25 @@ def long_local_393216():
             "oracle_seconds": round(time.time() - t0, 1)}
 
 
+def long_local_262144_cigar():
+    """The canonical CIGAR of the 262144 x 262144 local affine pair, from the oracle's linear-space traceback
+    (every 512th row kept, one block of full matrices at a time): begin and end cells, the run count and
+    the SHA-256 of the CIGAR words (little-endian uint32, (length << 4) | op), with the first and last runs."""
+    import hashlib
+    import numpy as np
+    w = synth.long_dna_local(seed=2, n=262144)
+    a, b = w.pair(0)
+    t0 = time.time()
+    r = oracle.align(_sc(w), a, b, traceback=True, impl="checkpointed", block_rows=512)
+    words = np.array([(L << 4) | op for L, op in r.cigar], dtype="<u4")
+    return {"workload": "long_dna_local(seed=2, n=262144)", "mode": "local", "gap_open": -3, "gap_extend": -1,
+            "match": 2, "mismatch": -3, "score": r.score, "q_begin": r.q_begin, "q_end": r.q_end,
+            "s_begin": r.s_begin, "s_end": r.s_end, "cigar_len": len(r.cigar),
+            "cigar_sha256": hashlib.sha256(words.tobytes()).hexdigest(),
+            "cigar_head": oracle.cigar_string(r.cigar[:12]), "cigar_tail": oracle.cigar_string(r.cigar[-12:]),
+            "oracle_seconds": round(time.time() - t0, 1)}
+
+
 def global_1k():
     """The 1000 x 1000 global linear DNA pair with its canonical CIGAR."""
     w = synth.long_dna_global_1k(seed=1)
@@ -131,7 +150,8 @@ def serve_sample():
     return out
 
 
-JOBS = {"long_local_262144": long_local_262144, "long_local_393216": long_local_393216, "global_1k": global_1k, "reads_sample": reads_sample,
+JOBS = {"long_local_262144": long_local_262144, "long_local_393216": long_local_393216,
+        "long_local_262144_cigar": long_local_262144_cigar, "global_1k": global_1k, "reads_sample": reads_sample,
         "protein_sample": protein_sample, "reads_digest": reads_digest, "protein_digest": protein_digest,
         "serve_sample": serve_sample}
 

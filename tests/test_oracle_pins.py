@@ -204,3 +204,40 @@ def test_batch_driver_matches_single():
         assert (res["score"][k], res["q_begin"][k], res["q_end"][k]) == (r.score, r.q_begin, r.q_end)
         got = [(int(x) >> 4, int(x) & 15) for x in cig[coff[k]:coff[k] + res["cigar_len"][k]]]
         assert got == r.cigar
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_checkpointed_traceback_equals_brute_force(seed):
+    """The oracle's linear-space traceback (kept rows every K rows, one block recomputed at a time) against
+    the brute-force enumeration, with blocks of 1, 2 and 3 rows, so walks cross block boundaries in every
+    state."""
+    for mode, A, sig, go, ge, q, s in _cases(100 + seed, 200, 6):
+        sc = oracle.Scoring.matrix(mode, sig, go, ge)
+        b = brute_align(mode, sig, go, ge, q, s)
+        for K in (1, 2, 3):
+            r = oracle.align(sc, q, s, traceback=True, impl="checkpointed", block_rows=K)
+            assert (r.score, r.q_begin, r.q_end, r.s_begin, r.s_end, r.cigar) == (
+                b.score, b.q_begin, b.q_end, b.s_begin, b.s_end, b.cigar), (K, mode, go, ge, list(q), list(s))
+
+
+def test_checkpointed_traceback_equals_full_matrices():
+    """Larger related pairs (up to 400 letters, long gaps) against the full-matrix traceback, every mode and
+    gap model, block heights from 1 row to more than the pair."""
+    import synth
+    rng = np.random.default_rng(11)
+    for trial in range(60):
+        mode = MODES[trial % 3]
+        A = int(rng.choice([4, 20]))
+        go, ge = (0, -1) if trial % 4 == 0 else (-int(rng.integers(1, 12)), -int(rng.integers(1, 3)))
+        sig = rng.integers(-4, 3, (A, A)).astype(np.int32)
+        np.fill_diagonal(sig, rng.integers(2, 9, A))
+        sc = oracle.Scoring.matrix(mode, sig, go, ge)
+        n = int(rng.integers(0, 400))
+        q = rng.integers(0, A, n, dtype=np.uint8)
+        s = synth.mutate_geometric(rng, q, 0.1, 0.03, 6.0, A)[:int(rng.integers(0, 400))] if n else \
+            rng.integers(0, A, int(rng.integers(0, 50)), dtype=np.uint8)
+        f = oracle.align(sc, q, s, traceback=True)
+        for K in (1, 5, 64, 1000):
+            r = oracle.align(sc, q, s, traceback=True, impl="checkpointed", block_rows=K)
+            assert (r.score, r.q_begin, r.q_end, r.s_begin, r.s_end, r.cigar) == (
+                f.score, f.q_begin, f.q_end, f.s_begin, f.s_end, f.cigar), (trial, K)
