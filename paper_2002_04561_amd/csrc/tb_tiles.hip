@@ -11,6 +11,7 @@
 // segment only; then one wave walks the segment (walk_wave.h) and hands its position to the next
 // segment up.  Each cell is relaxed again at most once, so the whole traceback relaxes at most twice
 // the cells of the matrix; memory is one segment of codes plus the checkpoints, not a code per cell.
+#include "band.h"
 #include "internal.h"
 #include "walk_wave.h"
 
@@ -21,8 +22,7 @@ constexpr int kTBlk = 32;      // steps between lane-0 input refills
 constexpr int kTRing = 256;    // columns held by the ring between two bands of a tile
 constexpr int kTWaves = kTileRows / kWfBand;  // bands (waves) of a tile
 
-// Same profile kinds as the band wavefront: register bytes for up to 4 letters, else an LDS table.
-constexpr int kTProfTable = 0, kTProfReg = 1;
+// Profile kinds of the band wavefront (band.h): register bytes for up to 4 letters, else the LDS table.
 
 __device__ __forceinline__ int t_dpp_shr1(int old, int src) {
   return __builtin_amdgcn_update_dpp(old, src, 0x138, 0xf, 0xf, false);  // wave_shr:1, lane 0 keeps old
@@ -111,7 +111,7 @@ __global__ __launch_bounds__(64 * kTWaves) void tb_tile_kernel(const KParams P, 
       c = Q[i - 1];
       if (c >= P.alphabet) c = kPad;
     }
-    if (PROF == kTProfReg) {
+    if (PROF == kProfReg) {
       uint32_t w = 0;
       for (int a = 0; a < 4; ++a) {
         const int v = (c < P.alphabet && a < P.alphabet) ? tab[c * kTab + a] : -128;
@@ -157,8 +157,8 @@ __global__ __launch_bounds__(64 * kTWaves) void tb_tile_kernel(const KParams P, 
   auto letter_idx = [&](int col) -> int {
     if (col > cols) return 0;
     int c = s[col - 1];
-    if (c >= P.alphabet) c = PROF == kTProfTable ? kPad : 0;
-    return PROF == kTProfReg ? c * 8 : c;
+    if (c >= P.alphabet) c = PROF == kProfTable ? kPad : 0;
+    return PROF == kProfReg ? c * 8 : c;
   };
 
   const int steps = cols + 63;
@@ -202,28 +202,12 @@ __global__ __launch_bounds__(64 * kTWaves) void tb_tile_kernel(const KParams P, 
       const int in_c = t_dpp_shr1(in_top_c, cur_c);
       cur_c = in_c;
       if (!decltype(checked)::value || (jt >= 1 && jt <= cols)) {
-        int32_t hd = diag, hup = in_h, eup = in_e;
+        int32_t hup = in_h, eup = in_e, hn = 0, unused_bv[R];
+        int unused_bj[R];
         uint32_t word = 0;
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-          const int32_t hlo = hl[r];
-          const int32_t e = AFFINE ? max(eup, hup + go) : hup;
-          const int32_t ff = AFFINE ? max(f[r] + ge, hlo + goe) : hlo + ge;
-          const int32_t sg = PROF == kTProfReg ? __builtin_amdgcn_sbfe(prof[r], in_c, 8) : tab[prof[r] + in_c];
-          const int32_t d = hd + sg;
-          int32_t h = max(d, max(e, ff));
-          if (MODE == ALN_LOCAL) h = max(h, nu[r]);
-          uint32_t src = (d == h) ? 0u : ((e == h) ? 1u : 2u);
-          if (MODE == ALN_LOCAL && h == nu[r]) src = 3u;
-          const uint32_t xe = AFFINE ? (uint32_t)(hup + go != e) : 0u;
-          const uint32_t xf = AFFINE ? (uint32_t)(hlo + goe != ff) : 0u;
-          word |= (src | (xe << 2) | (xf << 3)) << (4 * r);
-          f[r] = ff;
-          hl[r] = h;
-          hd = hlo;
-          hup = h;
-          eup = e;
-        }
+        band_column<MODE, AFFINE, PROF, true, decltype(checked)::value, R, false>(
+            tab, prof, in_c, 0, go, ge, goe, nu, hl, f, unused_bv, unused_bj, nullptr, jt, -1, diag, hup, eup, hn,
+            word);
         codes[jt - 1] = (uint16_t)word;
         bot_h = hup;
         bot_e = eup;
@@ -338,14 +322,14 @@ void launch_rounds(const KParams& kp, const uint8_t* q, const uint8_t* s, const 
       ProfScope prof("traceback_tiles", stream);
       if (kp.go != 0) {
         if (bytes && kp.alphabet <= 4)
-          launch_tiles<MODE, true, kTProfReg>(kp, q, s, V, seg, stream);
+          launch_tiles<MODE, true, kProfReg>(kp, q, s, V, seg, stream);
         else
-          launch_tiles<MODE, true, kTProfTable>(kp, q, s, V, seg, stream);
+          launch_tiles<MODE, true, kProfTable>(kp, q, s, V, seg, stream);
       } else {
         if (bytes && kp.alphabet <= 4)
-          launch_tiles<MODE, false, kTProfReg>(kp, q, s, V, seg, stream);
+          launch_tiles<MODE, false, kProfReg>(kp, q, s, V, seg, stream);
         else
-          launch_tiles<MODE, false, kTProfTable>(kp, q, s, V, seg, stream);
+          launch_tiles<MODE, false, kProfTable>(kp, q, s, V, seg, stream);
       }
     }
     ProfScope prof("traceback_walk", stream);

@@ -22,6 +22,7 @@
 #include <type_traits>
 
 #include "internal.h"
+#include "band.h"
 #include "walk.h"
 #include "walk_wave.h"
 
@@ -41,14 +42,6 @@ constexpr int kBlkGrouped = 32;                       // steps between lane-0 in
 constexpr int kCourierChunk = 32;                     // columns a courier moves between HBM and LDS at once
 constexpr int kWfBlockAlone = 64 * kWfWavesPerBlock;  // bands on their own: no courier
 
-// Where a band's substitution scores sigma(row letter, column letter) - ge come from:
-//   kProfTable  a 32-bit LDS table indexed by both letters (any score range);
-//   kProfReg    alphabets of up to 4 letters: one register per row holds the scores of the row's
-//               letter against the 4 letters as signed bytes, picked with a bit-field extract;
-//   kProfLane   alphabets of up to 32 letters: per letter, every lane keeps the scores of its
-//               R = 4 rows as 4 signed bytes in one LDS word, so a step reads one word.
-// The byte forms need every sigma - ge in -127..127 (-128 marks rows past the end).
-constexpr int kProfTable = 0, kProfReg = 1, kProfLane = 2;
 
 __device__ __forceinline__ int dpp_shr1(int old, int src) {
   return __builtin_amdgcn_update_dpp(old, src, 0x138, 0xf, 0xf, false);  // wave_shr:1, lane 0 keeps old
@@ -310,41 +303,8 @@ __global__ __launch_bounds__(kWfBlockAlone) void wf_i32_kernel(const KParams P, 
           int32_t hn = 0;
           uint32_t word = 0;
           const int pw = PROF == kProfLane ? (int)lp[in_c] : 0;
-#pragma unroll
-          for (int r = 0; r < R; ++r) {
-            const int32_t hlo = hl[r];
-            const int32_t e = AFFINE ? max(eup, hup + go) : hup;
-            const int32_t ff = AFFINE ? max(f[r] + ge, hlo + goe) : hlo + ge;
-            const int32_t sg = PROF == kProfReg    ? __builtin_amdgcn_sbfe(prof[r], in_c, 8)
-                               : PROF == kProfLane ? __builtin_amdgcn_sbfe(pw, 8 * r, 8)
-                                                   : tab[prof[r] + in_c];
-            const int32_t d = hd + sg;
-            int32_t h = max(d, max(e, ff));
-            if (MODE == ALN_LOCAL) h = max(h, nu[r]);
-            if (TB) {
-              uint32_t src = (d == h) ? 0u : ((e == h) ? 1u : 2u);
-              if (MODE == ALN_LOCAL && h == nu[r]) src = 3u;
-              const uint32_t xe = AFFINE ? (uint32_t)(hup + go != e) : 0u;
-              const uint32_t xf = AFFINE ? (uint32_t)(hlo + goe != ff) : 0u;
-              word |= (src | (xe << 2) | (xf << 3)) << (4 * r);
-            }
-            if (MODE == ALN_LOCAL) {
-              if (decltype(checked)::value) {
-                if (h > bv[r]) {
-                  bv[r] = h;
-                  bj[r] = j;
-                }
-              } else {
-                hk[r] = h;
-              }
-            }
-            if (MODE == ALN_SEMIGLOBAL && r == rn) hn = h;
-            f[r] = ff;
-            hl[r] = h;
-            hd = hlo;
-            hup = h;
-            eup = e;
-          }
+          band_column<MODE, AFFINE, PROF, TB, decltype(checked)::value, R>(tab, prof, in_c, pw, go, ge, goe, nu, hl, f, bv,
+                                                                          bj, hk, j, rn, hd, hup, eup, hn, word);
           if (TB) codes[j - 1] = (uint16_t)word;
           if (MODE == ALN_SEMIGLOBAL && last_band && rn >= 0 && rn < R && hn > brow) {
             brow = hn;
@@ -1064,41 +1024,8 @@ __global__ __launch_bounds__(kWfBlock) void wf_i32_group_kernel(const KParams P,
           int32_t hn = 0;
           uint32_t word = 0;
           const int pw = PROF == kProfLane ? (int)lp[in_c] : 0;
-#pragma unroll
-          for (int r = 0; r < R; ++r) {
-            const int32_t hlo = hl[r];
-            const int32_t e = AFFINE ? max(eup, hup + go) : hup;
-            const int32_t ff = AFFINE ? max(f[r] + ge, hlo + goe) : hlo + ge;
-            const int32_t sg = PROF == kProfReg    ? __builtin_amdgcn_sbfe(prof[r], in_c, 8)
-                               : PROF == kProfLane ? __builtin_amdgcn_sbfe(pw, 8 * r, 8)
-                                                   : tab[prof[r] + in_c];
-            const int32_t d = hd + sg;
-            int32_t h = max(d, max(e, ff));
-            if (MODE == ALN_LOCAL) h = max(h, nu[r]);
-            if (TB) {
-              uint32_t src = (d == h) ? 0u : ((e == h) ? 1u : 2u);
-              if (MODE == ALN_LOCAL && h == nu[r]) src = 3u;
-              const uint32_t xe = AFFINE ? (uint32_t)(hup + go != e) : 0u;
-              const uint32_t xf = AFFINE ? (uint32_t)(hlo + goe != ff) : 0u;
-              word |= (src | (xe << 2) | (xf << 3)) << (4 * r);
-            }
-            if (MODE == ALN_LOCAL) {
-              if (decltype(checked)::value) {
-                if (h > bv[r]) {
-                  bv[r] = h;
-                  bj[r] = j;
-                }
-              } else {
-                hk[r] = h;
-              }
-            }
-            if (MODE == ALN_SEMIGLOBAL && r == rn) hn = h;
-            f[r] = ff;
-            hl[r] = h;
-            hd = hlo;
-            hup = h;
-            eup = e;
-          }
+          band_column<MODE, AFFINE, PROF, TB, decltype(checked)::value, R>(tab, prof, in_c, pw, go, ge, goe, nu, hl, f, bv,
+                                                                          bj, hk, j, rn, hd, hup, eup, hn, word);
           if (TB) codes[j - 1] = (uint16_t)word;
           if (MODE == ALN_SEMIGLOBAL && last_band && rn >= 0 && rn < R && hn > brow) {
             brow = hn;
@@ -1122,23 +1049,18 @@ __global__ __launch_bounds__(kWfBlock) void wf_i32_group_kernel(const KParams P,
         const int4 vh = reinterpret_cast<const int4*>(st_h)[g4];
         const int4 ve = reinterpret_cast<const int4*>(st_e)[g4];
         const int4 vc = reinterpret_cast<const int4*>(st_c)[g4];
-        if (t0 >= 63 && t0 + 3 < m) {
+        // With checkpoints, some lane's column in these 4 steps is a multiple of kTileCols only when
+        // (t0 + 1) mod kTileCols is below 64 or within 3 of kTileCols (a wave-uniform test); such
+        // groups take the checked path, which stores the checkpoints, and the fast path stays as is.
+        const int u = (t0 + 1) & (kTileCols - 1);
+        const bool ck_group = CKPT && (u < 64 || u > kTileCols - 4);
+        if (t0 >= 63 && t0 + 3 < m && !ck_group) {
           // every lane is inside the matrix: no range test; local optima are tracked per 4 steps
           int32_t hk[4][R];
-          // some lane's column in these 4 steps is a multiple of kTileCols only when (t0 + 1) mod
-          // kTileCols is below 64 or within 3 of kTileCols (a wave-uniform test)
-          const int u = (t0 + 1) & (kTileCols - 1);
-          if (CKPT && (u < 64 || u > kTileCols - 4)) {
-            step(t0, vh.x, ve.x, vc.x, std::false_type(), hk[0], true);
-            step(t0 + 1, vh.y, ve.y, vc.y, std::false_type(), hk[1], true);
-            step(t0 + 2, vh.z, ve.z, vc.z, std::false_type(), hk[2], true);
-            step(t0 + 3, vh.w, ve.w, vc.w, std::false_type(), hk[3], true);
-          } else {
-            step(t0, vh.x, ve.x, vc.x, std::false_type(), hk[0], false);
-            step(t0 + 1, vh.y, ve.y, vc.y, std::false_type(), hk[1], false);
-            step(t0 + 2, vh.z, ve.z, vc.z, std::false_type(), hk[2], false);
-            step(t0 + 3, vh.w, ve.w, vc.w, std::false_type(), hk[3], false);
-          }
+          step(t0, vh.x, ve.x, vc.x, std::false_type(), hk[0], false);
+          step(t0 + 1, vh.y, ve.y, vc.y, std::false_type(), hk[1], false);
+          step(t0 + 2, vh.z, ve.z, vc.z, std::false_type(), hk[2], false);
+          step(t0 + 3, vh.w, ve.w, vc.w, std::false_type(), hk[3], false);
           if (MODE == ALN_LOCAL) {
             int32_t mk[R];
             bool imp = false;

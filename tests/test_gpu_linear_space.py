@@ -3,8 +3,9 @@ of codes): checkpoint rows and columns kept by the forward pass, tiles relaxed a
 bottom first, and walked.  The canonical CIGAR, begin and end cells must equal the oracle's (full
 matrices, Sec. III-A) on every shape; a small code budget forces segments of 1024 rows, so walks cross
 many segment and tile boundaries, inside gaps too.  At full size the linear-space CIGAR of the 262144^2
-pair equals the one of the stored-code walk, and a pair whose codes would take 72 GiB comes back with a
-CIGAR that re-scores to the oracle's score and end cell."""
+pair equals the one of the stored-code walk and the oracle's canonical CIGAR (its own linear-space
+traceback, stored as a digest), and a pair whose codes would take 72 GiB comes back with a CIGAR that
+re-scores to the oracle's score and end cell."""
 import json
 import os
 
@@ -151,6 +152,20 @@ def test_linear_space_full_262144_equals_stored_codes(gpu):
     assert (total, i, j) == (ls[0], ls[2], ls[4])
     st = _run_ls(a, b, 1, 4, -3, -1, 2, -3, linear=False)
     assert st == ls
+    _check_canonical(ls)
+
+
+def _check_canonical(got):
+    """The full-size canonical alignment from the oracle's linear-space traceback (stored as a digest)."""
+    import hashlib
+    path = os.path.join(HERE, "golden", "long_local_262144_cigar.json")
+    if not os.path.exists(path):
+        pytest.skip("canonical CIGAR of the full pair not generated")
+    g = json.load(open(path))
+    words = np.array([(L << 4) | op for L, op in got[5]], dtype="<u4")
+    assert (got[0], got[1], got[2], got[3], got[4], len(got[5])) == (
+        g["score"], g["q_begin"], g["q_end"], g["s_begin"], g["s_end"], g["cigar_len"])
+    assert hashlib.sha256(words.tobytes()).hexdigest() == g["cigar_sha256"]
 
 
 @pytest.mark.slow
