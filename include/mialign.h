@@ -120,6 +120,14 @@ aln_status_t aln_batch_workspace_size(const aln_scoring_t* scoring, int64_t n_pa
  * instead, all of them sharing one device-wide work queue (the dynamic wavefront of Sec. IV-A),
  * largest first.  The routing is decided on the device, so the host needs no copy of the lengths;
  * aln_align_batch_ex sets the threshold and the other execution choices.
+ * In traceback calls the rule is fixed: pairs with n*m >= 2^18, or longer than 1024 on either side,
+ * run on the band wavefront and store their 4-bit predecessor codes in an arena of the workspace (about
+ * n*m/2 bytes each); the one-pair-per-lane kernels then hold code slabs for pairs up to 1024 x 1024
+ * only.  The arena is sized by a bound from max_n, max_m, total_q and total_s; where that bound exceeds
+ * the arena budget (aln_set_batch_code_arena, 16 GiB by default) the arena is the budget, pairs take
+ * room in the order they reach it, those that find none run one pair per lane, and the lanes' slabs are
+ * sized for max_n x max_m (fewer waves in flight, at most 8 GiB of slabs).  Results are identical
+ * either way.
  *   q, s          DEVICE  concatenated uint8 codes of all queries / subjects
  *   q_off, s_off  DEVICE  int64[n_pairs+1]; pair k is q[q_off[k]:q_off[k+1]] vs s[s_off[k]:s_off[k+1]]
  *   max_n, max_m  upper bounds of the lengths (pairs above them get ALN_RES_TOO_LONG)
@@ -270,6 +278,12 @@ aln_status_t aln_long_workspace_size(const aln_scoring_t* scoring, int64_t n, in
 aln_status_t aln_align_long(const aln_scoring_t* scoring, const uint8_t* q, int64_t n, const uint8_t* s, int64_t m,
                             uint32_t flags, aln_result_t* out, uint32_t* cigar, int64_t cigar_capacity,
                             void* workspace, size_t workspace_bytes, hipStream_t stream);
+
+/* Most bytes the code arena of a traceback batch (aln_align_batch with ALN_TRACEBACK) may take; the arena
+ * holds the predecessor codes of the pairs that run on the band wavefront.  0 restores the default of
+ * 16 GiB.  Process-wide; read when a size query or align call is made, so the same value must hold for
+ * both.  Returns ALN_E_INVALID for a negative size. */
+aln_status_t aln_set_batch_code_arena(int64_t bytes);
 
 /* Bytes of 4-bit predecessor codes a linear-space traceback (aln_align_long with ALN_LINEAR_SPACE, or
  * above 64 GiB of codes) holds at once: the rows of a segment that the traceback relaxes again in one go

@@ -97,6 +97,7 @@ _SIGNATURES = {
                                                  ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "aln_noalloc_scratch_bytes": (ctypes.c_size_t, []),
     "aln_set_traceback_budget": (ctypes.c_int32, [ctypes.c_int64]),
+    "aln_set_batch_code_arena": (ctypes.c_int32, [ctypes.c_int64]),
     "aln_traceback_workspace_size": (ctypes.c_int32, [ctypes.POINTER(aln_scoring_t), ctypes.c_int64, ctypes.c_int64,
                                                       ctypes.c_int64, ctypes.POINTER(ctypes.c_size_t)]),
     "aln_traceback": (ctypes.c_int32, [ctypes.POINTER(aln_scoring_t), ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
@@ -333,6 +334,13 @@ def aln_set_traceback_budget(nbytes: int = 0) -> None:
     st = lib().aln_set_traceback_budget(nbytes)
     if st != 0:
         raise AlnError(st, "aln_set_traceback_budget")
+
+
+def aln_set_batch_code_arena(nbytes: int = 0) -> None:
+    """Most bytes of a traceback batch's code arena (0 = the library's default, 16 GiB)."""
+    st = lib().aln_set_batch_code_arena(nbytes)
+    if st != 0:
+        raise AlnError(st, "aln_set_batch_code_arena")
 
 
 def aln_set_wait_limits(device_polls: int = 0, lds_polls: int = 0) -> None:

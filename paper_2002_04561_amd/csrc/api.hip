@@ -117,7 +117,7 @@ __global__ void fill_i32_kernel(int* p, int n, int v) {
 // Workspace of a batch call:
 //   [slabs: shared by the 16-bit kernel and the 32-bit kernel, which run one after the other]
 //   [redo list: n_pairs ints + counter]
-//   [split plan + wavefront engine (score-only calls)]
+//   [split plan + wavefront engine, with a code arena for traceback calls]
 struct BatchLayout {
   BatchPlan bp;
   BatchPlan16 bp16;
@@ -129,12 +129,19 @@ struct BatchLayout {
 static aln_status_t batch_layout(const KParams& kp, int64_t n_pairs, int64_t max_n, int64_t max_m, int64_t total_q,
                                  int64_t total_s, uint32_t flags, const BatchCfg& cfg, BatchLayout* L) {
   const bool tb = (flags & ALN_TRACEBACK) != 0;
-  aln_status_t st = plan_batch_i32(kp, n_pairs, max_n, max_m, tb, &L->bp);
+  aln_status_t st = plan_split(n_pairs, total_q, total_s, tb, max_n, max_m, cfg, &L->sp);
   if (st != ALN_OK) return st;
-  L->use16 = !(flags & ALN_FORCE_INT32) && cfg.small16 && max_m < 32767;
+  // The one-pair-per-lane kernels of a traceback call meet pairs up to kTbLaneDim on each side when the
+  // wavefront's code arena takes every longer pair; their slabs are sized for that.
+  const bool lanes_bounded = tb && L->sp.code_exact;
+  const int64_t lane_n = lanes_bounded ? std::min(max_n, kTbLaneDim) : max_n;
+  const int64_t lane_m = lanes_bounded ? std::min(max_m, kTbLaneDim) : max_m;
+  st = plan_batch_i32(kp, n_pairs, lane_n, lane_m, tb, &L->bp);
+  if (st != ALN_OK) return st;
+  L->use16 = !(flags & ALN_FORCE_INT32) && cfg.small16 && lane_m < 32767;
   size_t slabs = L->bp.total_bytes;
   if (L->use16) {
-    st = plan_batch_i16(kp, n_pairs, max_n, max_m, tb, &L->bp16);
+    st = plan_batch_i16(kp, n_pairs, lane_n, lane_m, tb, &L->bp16);
     if (st != ALN_OK) return st;
     if (L->bp16.total_bytes > slabs) slabs = L->bp16.total_bytes;
   }
@@ -144,8 +151,6 @@ static aln_status_t batch_layout(const KParams& kp, int64_t n_pairs, int64_t max
   L->off_redo_cnt = off;
   off += 256;
   L->off_split = off;
-  st = plan_split(n_pairs, tb ? 0 : total_q, tb ? 0 : total_s, !tb, cfg, &L->sp);
-  if (st != ALN_OK) return st;
   off += L->sp.total_bytes;
   L->total = off;
   return ALN_OK;
@@ -214,13 +219,14 @@ aln_status_t aln_align_batch_ex(const aln_scoring_t* scoring, int64_t n_pairs, c
   int* redo_idx = reinterpret_cast<int*>(base + L.off_redo);
   int* redo_cnt = reinterpret_cast<int*>(base + L.off_redo_cnt);
 
-  // the inter-sequence kernels see a shape-sorted list: all pairs of a traceback call, the small
-  // ones of a score-only call (whose large pairs go to the wavefront engine)
+  // The inter-sequence kernels see a shape-sorted list of the small pairs; the large ones go to the
+  // wavefront engine (in a traceback call, those whose codes found room in its arena).
   char* split_ws = base + L.off_split;
   launch_split(L.sp, n_pairs, q_off, s_off, max_n, max_m, out, split_ws, stream);
-  if (!tb) {
+  if (!tb || L.sp.code_cap > 0) {
     WfWs W = wf_view(split_ws + L.sp.wf_base, L.sp.wf);
-    st = launch_wf_i32(kp, W, q, s, out, L.sp.wf_waves, L.sp.grouped, false, L.sp.wf_p16, nullptr, 0, stream);
+    st = launch_wf_i32(kp, W, q, s, out, L.sp.wf_waves, L.sp.grouped, tb, !tb && L.sp.wf_p16, cigar, 0, stream,
+                       tb ? cigar_off : nullptr);
     if (st != ALN_OK) return st;
   }
   const int* list = reinterpret_cast<const int*>(split_ws + L.sp.off_small_idx);
@@ -385,6 +391,12 @@ static const uint32_t kLongFlags = ALN_TRACEBACK | ALN_FORCE_INT32 | ALN_FORCE_I
 
 // Bytes of predecessor codes a linear-space traceback holds at once (aln_set_traceback_budget).
 static int64_t g_ls_budget = kLsCodeBudget;
+
+aln_status_t aln_set_batch_code_arena(int64_t bytes) {
+  if (bytes < 0) return ALN_E_INVALID;
+  g_tb_arena_bytes = bytes ? bytes : kTbArenaBytes;
+  return ALN_OK;
+}
 
 aln_status_t aln_set_traceback_budget(int64_t bytes) {
   if (bytes < 0) return ALN_E_INVALID;

@@ -25,6 +25,8 @@ struct SplitView {
   int* counters;   // [0] small pairs, [1] big pairs
   int* keys;       // per pair: sort key
   int* hist;       // [kKeys] counts, then cursors
+  int64_t* code_off;                 // traceback calls: per pair, offset of its codes in the code arena
+  unsigned long long* code_used;     // traceback calls: code words reserved so far
 };
 
 // 8 bins per octave: floor(8 * log2(x)) - 16 for x >= 8, x itself below.
@@ -58,6 +60,7 @@ __device__ __forceinline__ bool orient_flip(int64_t n, int64_t m, int orient) {
 __global__ void split_reset_kernel(SplitView V) {
   for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < kKeys; k += gridDim.x * blockDim.x) V.hist[k] = 0;
   if (blockIdx.x == 0 && threadIdx.x < 2) V.counters[threadIdx.x] = 0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) *V.code_used = 0;
 }
 
 // Blocks of the classify and scatter passes each own one contiguous chunk of pairs and count its
@@ -75,7 +78,8 @@ __global__ __launch_bounds__(kPlanThreads) void split_classify_kernel(int64_t n_
                                                                       const int64_t* __restrict__ q_off,
                                                                       const int64_t* __restrict__ s_off,
                                                                       int64_t max_n, int64_t max_m,
-                                                                      int64_t big_cells, int orient, SplitView V) {
+                                                                      int64_t big_cells, int64_t lane_dim, int orient,
+                                                                      bool tb, int64_t code_cap, SplitView V) {
   __shared__ int h[kKeys];
   __shared__ int n_big;
   for (int k = threadIdx.x; k < kKeys; k += blockDim.x) h[k] = 0;
@@ -87,7 +91,20 @@ __global__ __launch_bounds__(kPlanThreads) void split_classify_kernel(int64_t n_
     const int64_t n = q_off[p + 1] - q_off[p], m = s_off[p + 1] - s_off[p];
     const bool fits = n >= 0 && m >= 0 && n <= max_n && m <= max_m;
     int key;
-    if (fits && n > 0 && m > 0 && n * m >= big_cells) {
+    // (a traceback call's pair longer than lane_dim on a side goes to the wavefront even with the
+    // other side empty: it then has no bands, and the finish pass gives its result)
+    bool big = fits && ((n > 0 && m > 0 && n * m >= big_cells) || n > lane_dim || m > lane_dim);
+    if (big && tb) {
+      // a traceback call: the pair's 4-bit codes (one 16-bit word per band lane and column) must fit the
+      // code arena; pairs are given room in the order they reserve it.  A pair that finds no room runs
+      // one pair per lane instead, with the same result: the planner sizes the lanes' slabs for every
+      // pair whenever the arena may fall short.
+      const unsigned long long words = (unsigned long long)((n + kWfBand - 1) / kWfBand) * 64ull * (unsigned long long)m;
+      const unsigned long long at = code_cap > 0 ? atomicAdd(V.code_used, words) : 0ull;
+      big = code_cap > 0 && at + words <= (unsigned long long)code_cap;
+      if (big) V.code_off[p] = (int64_t)at;
+    }
+    if (big) {
       // wavefront pairs by band work, bands x (columns + 63), largest first: a workgroup relaxes
       // kWfWavesPerBlock consecutive bands, which then take about the same time
       const bool flip = orient_flip(n, m, orient);
@@ -139,7 +156,7 @@ __global__ __launch_bounds__(kScanThreads) void sort_scan_kernel(SplitView V) {
 __global__ __launch_bounds__(kPlanThreads) void sort_scatter_kernel(int64_t n_pairs,
                                                                     const int64_t* __restrict__ q_off,
                                                                     const int64_t* __restrict__ s_off, int orient,
-                                                                    SplitView V, WfWs W) {
+                                                                    int64_t code_cap, SplitView V, WfWs W) {
   __shared__ int h[kKeys];  // this chunk's count per key, then its next position per key
   const int n_big = V.counters[1];
   for (int k = threadIdx.x; k < kKeys; k += blockDim.x) h[k] = 0;
@@ -172,7 +189,7 @@ __global__ __launch_bounds__(kPlanThreads) void sort_scatter_kernel(int64_t n_pa
     pr.pad_ = 0;
     pr.item0 = 0;
     pr.row_off = 0;
-    pr.code_off = 0;
+    pr.code_off = code_cap > 0 ? V.code_off[p] : 0;
     W.pairs[pos] = pr;
   }
 }
@@ -234,8 +251,11 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 }  // namespace
 
+int64_t g_tb_arena_bytes = kTbArenaBytes;
+
 BatchCfg resolve_cfg(const aln_batch_config_t* c) {
   BatchCfg r;
+  r.tb_arena = g_tb_arena_bytes;
   r.wf_min_cells = 0;
   r.wf_group = 0;
   r.wf_waves_per_cu = kWfWavesPerCUDefault;
@@ -259,11 +279,17 @@ BatchCfg resolve_cfg(const aln_batch_config_t* c) {
   return r;
 }
 
-aln_status_t plan_split(int64_t n_pairs, int64_t total_q, int64_t total_s, bool route_big, const BatchCfg& cfg,
-                        SplitPlan* sp) {
+aln_status_t plan_split(int64_t n_pairs, int64_t total_q, int64_t total_s, bool tb, int64_t max_n, int64_t max_m,
+                        const BatchCfg& cfg, SplitPlan* sp) {
   const int cus = device_cu_count();
   int64_t min_cells = cfg.wf_min_cells;
-  if (min_cells == 0) {
+  if (tb) {
+    // Traceback calls send pairs from kTbMinCells cells up to the band wavefront, with their codes in an
+    // arena: the one-pair-per-lane kernels hold a code slab per wave for the largest pair they may meet,
+    // so such pairs would cost every wave their size.  The rule is fixed, so that the workspace does
+    // not depend on the call's configuration.
+    min_cells = kTbMinCells;
+  } else if (min_cells == 0) {
     // The one-pair-per-lane kernels keep 8 waves of 128 pairs (16-bit lanes) on each compute unit.
     // A batch with fewer pairs leaves waves idle there, and each wave pads its pairs to the largest n
     // and m among them, so such a batch sends its pairs from 2^12 cells up to the band wavefront,
@@ -271,8 +297,28 @@ aln_status_t plan_split(int64_t n_pairs, int64_t total_q, int64_t total_s, bool 
     const int64_t fill = (int64_t)128 * 8 * (cus > 0 ? cus : 1);
     min_cells = n_pairs >= fill ? (int64_t)1 << 16 : (int64_t)1 << 12;
   }
-  sp->big_cells = route_big ? min_cells : INT64_MAX;
-  sp->orient = cfg.orient;
+  sp->tb = tb;
+  sp->big_cells = min_cells;
+  // A traceback call also sends every pair longer than kTbLaneDim on either side to the wavefront.
+  sp->lane_dim = tb ? kTbLaneDim : INT64_MAX;
+  // a traceback walks its pair as given: no transposed pairs
+  sp->orient = tb ? 0 : cfg.orient;
+  // Code arena of a traceback call.  A wavefront pair takes ceil(n / 256) x 64 x m words, at most
+  // n m / 4 + 64 m; summed over the batch that is at most min(total_q max_m, total_s max_n) / 4 +
+  // 64 total_s.  The arena holds that bound when it fits the arena budget (cfg.tb_arena bytes): then
+  // every wavefront pair finds room (code_exact), and the lanes' slabs need only hold pairs up to
+  // kTbLaneDim on each side.  Otherwise the arena is the budget and the lanes' slabs are sized for the
+  // largest pair.  None when no pair within the bounds can reach the wavefront.
+  sp->code_cap = 0;
+  sp->code_exact = true;
+  if (tb && max_n > 0 && max_m > 0 &&
+      (max_n * max_m >= min_cells || max_n > kTbLaneDim || max_m > kTbLaneDim)) {
+    const int64_t cells = std::min(total_q * max_m, total_s * max_n);
+    const int64_t words = cells / 4 + (int64_t)kWfBand / 4 * (total_s + 1);
+    const int64_t cap = cfg.tb_arena / 2;
+    sp->code_exact = words <= cap;
+    sp->code_cap = std::min<int64_t>(words, cap);
+  }
   size_t off = 0;
   sp->off_small_idx = off;
   off += align256((size_t)(n_pairs + 1) * sizeof(int));
@@ -282,13 +328,17 @@ aln_status_t plan_split(int64_t n_pairs, int64_t total_q, int64_t total_s, bool 
   off += align256((size_t)(n_pairs + 1) * sizeof(int));
   sp->off_hist = off;
   off += align256((size_t)kKeys * sizeof(int));
+  sp->off_code_off = off;
+  off += sp->code_cap > 0 ? align256((size_t)(n_pairs + 1) * sizeof(int64_t)) : 0;
+  sp->off_code_used = off;
+  off += 256;
   sp->wf_base = off;
   // bands run along the longer side when oriented: at most (n + m) / band + 1 per pair
   const int64_t max_items = (total_q + total_s) / kWfBand + n_pairs + 1;
   // a pair of two or more bands has row slots over its columns, never more than m + 1 of them
   sp->item_cap = max_items;
   sp->row_cap = 2 * (total_s + n_pairs);
-  off += wf_layout(n_pairs + 1, max_items, sp->row_cap, 0, &sp->wf);
+  off += wf_layout(n_pairs + 1, max_items, sp->row_cap, sp->code_cap, &sp->wf);
   sp->total_bytes = off;
   sp->wf_waves = wf_waves(cfg.wf_waves_per_cu);
   // Groups of bands pay off when the batch has few bands per SIMD: then each compute wave is alone
@@ -317,6 +367,8 @@ void launch_split(const SplitPlan& sp, int64_t n_pairs, const int64_t* q_off, co
   V.counters = reinterpret_cast<int*>(base + sp.off_small_cnt);
   V.keys = reinterpret_cast<int*>(base + sp.off_keys);
   V.hist = reinterpret_cast<int*>(base + sp.off_hist);
+  V.code_off = reinterpret_cast<int64_t*>(base + sp.off_code_off);
+  V.code_used = reinterpret_cast<unsigned long long*>(base + sp.off_code_used);
   WfWs W = wf_view(base + sp.wf_base, sp.wf);
   ProfScope prof("plan", stream);
   hipLaunchKernelGGL(split_reset_kernel, dim3(68), dim3(256), 0, stream, V);
@@ -324,10 +376,10 @@ void launch_split(const SplitPlan& sp, int64_t n_pairs, const int64_t* q_off, co
   int64_t blocks = (n_pairs + 4095) / 4096;
   blocks = blocks < 1 ? 1 : (blocks > 512 ? 512 : blocks);
   hipLaunchKernelGGL(split_classify_kernel, dim3((unsigned)blocks), dim3(kPlanThreads), 0, stream, n_pairs, q_off,
-                     s_off, max_n, max_m, sp.big_cells, sp.orient, V);
+                     s_off, max_n, max_m, sp.big_cells, sp.lane_dim, sp.orient, sp.tb, sp.code_cap, V);
   hipLaunchKernelGGL(sort_scan_kernel, dim3(1), dim3(kScanThreads), 0, stream, V);
   hipLaunchKernelGGL(sort_scatter_kernel, dim3((unsigned)blocks), dim3(kPlanThreads), 0, stream, n_pairs, q_off,
-                     s_off, sp.orient, V, W);
+                     s_off, sp.orient, sp.code_cap, V, W);
   hipLaunchKernelGGL(split_scan_kernel, dim3(1), dim3(1024), 0, stream, V, W, sp.item_cap, sp.row_cap, out);
 }
 

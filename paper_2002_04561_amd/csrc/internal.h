@@ -35,6 +35,11 @@ struct KParams {
 // Traceback slabs of the one-pair-per-lane kernels hold every cell's code for the waves in flight; a batch
 // of large pairs runs fewer waves rather than asking for more than this.
 constexpr int64_t kTbSlabBudget = (int64_t)8 << 30;
+// Codes of the pairs a traceback batch sends to the band wavefront are held in an arena of at most this.
+constexpr int64_t kTbArenaBytes = (int64_t)16 << 30;
+// ... namely every pair of at least kTbMinCells cells or longer than kTbLaneDim on a side.
+constexpr int64_t kTbMinCells = (int64_t)1 << 18;
+constexpr int64_t kTbLaneDim = 1024;
 
 constexpr int64_t kSpinDevDefault = 1ll << 22;  // ~0.1-0.5 s of polling device memory
 constexpr int64_t kSpinLdsDefault = 1ll << 26;  // ~1-2 s of polling LDS
@@ -163,9 +168,11 @@ WfWs wf_view(void* base, const WfOffsets& o);
 // grouped: workgroups of 4 consecutive bands with LDS hand-offs and a courier wave for HBM
 // p16: grouped score-only local bands over alphabets of up to 4 letters may use packed 16-bit cells
 // where the scoring's step bound keeps them exact
+// cigar_off: batches, each pair's CIGAR room (cigar[cigar_off[k] .. cigar_off[k + 1]]); else one pair with
+// cigar_cap words at cigar
 aln_status_t launch_wf_i32(const KParams& kp, const WfWs& W, const uint8_t* q, const uint8_t* s, aln_result_t* out,
                            int max_waves, bool grouped, bool tb, bool p16, uint32_t* cigar, int64_t cigar_cap,
-                           hipStream_t stream);
+                           hipStream_t stream, const int64_t* cigar_off = nullptr);
 aln_status_t plan_long(int64_t n, int64_t m, bool tb, LongPlan* plan);
 void launch_single_pair(const WfWs& W, int n, int m, hipStream_t stream);
 
@@ -196,8 +203,12 @@ struct SplitPlan {
   int64_t item_cap, row_cap;  // bands and row-slot entries the workspace holds
   bool grouped;               // the wavefront engine runs workgroups of 4 consecutive bands
   bool wf_p16;                // grouped score-only local bands may use packed 16-bit cells
+  bool tb;                    // a traceback call
+  int64_t lane_dim;           // traceback calls: pairs longer than this on a side go to the wavefront
+  int64_t code_cap;           // traceback calls: 16-bit code words the wavefront's arena holds (0: none)
+  bool code_exact;            // the arena holds the codes of every pair that goes to the wavefront
   WfOffsets wf;
-  size_t off_small_idx, off_small_cnt, off_keys, off_hist, wf_base, total_bytes;
+  size_t off_small_idx, off_small_cnt, off_keys, off_hist, off_code_off, off_code_used, wf_base, total_bytes;
   int wf_waves;
 };
 // Resolved execution choices of a batch call (defaults filled in).
@@ -209,10 +220,13 @@ struct BatchCfg {
   int orient;  // 1 longer along the rows, 0 as given, 2 the cheaper of the two
   bool small16;
   bool wf_p16;  // packed 16-bit wavefront bands where exact
+  int64_t tb_arena;  // most bytes of a traceback call's code arena (aln_set_batch_code_arena)
 };
+// Process-wide bound on a traceback batch's code arena (default kTbArenaBytes).
+extern int64_t g_tb_arena_bytes;
 BatchCfg resolve_cfg(const aln_batch_config_t* c);
-aln_status_t plan_split(int64_t n_pairs, int64_t total_q, int64_t total_s, bool route_big, const BatchCfg& cfg,
-                        SplitPlan* sp);
+aln_status_t plan_split(int64_t n_pairs, int64_t total_q, int64_t total_s, bool tb, int64_t max_n, int64_t max_m,
+                        const BatchCfg& cfg, SplitPlan* sp);
 void launch_split(const SplitPlan& sp, int64_t n_pairs, const int64_t* q_off, const int64_t* s_off, int64_t max_n,
                   int64_t max_m, aln_result_t* out, void* ws, hipStream_t stream);
 

@@ -1163,9 +1163,14 @@ __global__ __launch_bounds__(kWfBlock) void wf_i32_group_kernel(const KParams P,
 }
 
 // One wave per pair: reduces the pair's band optima into its aln_result_t.
+// cigar_off, when given, is a batch call's: pair out_idx owns cigar[cigar_off[out_idx] .. cigar_off[out_idx + 1]];
+// otherwise the single pair owns cigar_cap words at cigar.
 template <int MODE, bool TB>
-__global__ __launch_bounds__(256) void wf_finish_kernel(const KParams P, WfWs W, aln_result_t* __restrict__ out,
-                                                        uint32_t* __restrict__ cigar, int64_t cigar_cap) {
+__global__ __launch_bounds__(256) void wf_finish_kernel(const KParams P, WfWs W, const uint8_t* __restrict__ q,
+                                                        const uint8_t* __restrict__ s,
+                                                        aln_result_t* __restrict__ out,
+                                                        uint32_t* __restrict__ cigar, int64_t cigar_cap,
+                                                        const int64_t* __restrict__ cigar_off) {
   __shared__ uint16_t walk_win[TB ? 4 : 1][TB ? kWalkGroups * kWalkCols : 1];
   const int lane = threadIdx.x & 63;
   const int np = *W.n_pairs;
@@ -1181,6 +1186,15 @@ __global__ __launch_bounds__(256) void wf_finish_kernel(const KParams P, WfWs W,
         bi = v.y;
         bj = v.z;
       }
+    }
+    if (pr.nb == 0) {
+      // a pair with an empty side has no bands, whose relaxation checks the letters: check them here
+      const uint8_t* rq = (pr.flip ? s : q) + pr.q_off;  // the pair's row and column letters
+      const uint8_t* rs = (pr.flip ? q : s) + pr.s_off;
+      for (int k = lane; k < pr.n; k += 64)
+        if (rq[k] >= P.alphabet) flag |= 1;
+      for (int k = lane; k < pr.m; k += 64)
+        if (rs[k] >= P.alphabet) flag |= 1;
     }
     for (int o = 32; o >= 1; o >>= 1) {
       const int s2 = __shfl_xor(bs, o, 64), i2 = __shfl_xor(bi, o, 64), j2 = __shfl_xor(bj, o, 64);
@@ -1227,14 +1241,21 @@ __global__ __launch_bounds__(256) void wf_finish_kernel(const KParams P, WfWs W,
     if (TB && r.flags == 0) {
       // The codes form a [row group][column] array of 16-bit words, 4 rows per word (band bb, lane L
       // is row group bb * 64 + L); walk_core walks them with the whole wave.
+      uint32_t* cg = cigar;
+      int64_t cap = cigar_cap;
+      if (cigar_off) {
+        const int64_t c0 = cigar_off[pr.out_idx];
+        cg = cigar + c0;
+        cap = cigar_off[pr.out_idx + 1] - c0;
+      }
       WalkState S;
       walk_start(S, r.q_end, r.s_end);
-      walk_core<MODE>(W.codes + pr.code_off, m, 0, S, walk_win[threadIdx.x >> 6], lane, cigar, cigar_cap);
-      const int64_t runs = walk_finish(S, lane, cigar, cigar_cap);
+      walk_core<MODE>(W.codes + pr.code_off, m, 0, S, walk_win[threadIdx.x >> 6], lane, cg, cap);
+      const int64_t runs = walk_finish(S, lane, cg, cap);
       r.q_begin = S.i;
       r.s_begin = S.j;
       r.cigar_len = (int)runs;
-      if (runs > cigar_cap) r.flags |= ALN_RES_CIGAR_TRUNC;
+      if (runs > cap) r.flags |= ALN_RES_CIGAR_TRUNC;
       if (S.stuck) r.flags |= ALN_RES_DEVICE_ERROR;
     }
     if (lane == 0) out[pr.out_idx] = r;
@@ -1341,13 +1362,16 @@ void launch_wf_m(const KParams& kp, const uint8_t* q, const uint8_t* s, const Wf
 
 template <int MODE>
 void launch_wf_mode(const KParams& kp, const uint8_t* q, const uint8_t* s, const WfWs& W, int nw, bool grouped, bool tb,
-                    bool p16, aln_result_t* out, uint32_t* cigar, int64_t cap, hipStream_t st) {
+                    bool p16, aln_result_t* out, uint32_t* cigar, int64_t cap, const int64_t* cigar_off,
+                    hipStream_t st) {
   if (tb) {
     launch_wf_m<MODE, true>(kp, q, s, W, nw, grouped, false, st);
-    hipLaunchKernelGGL((wf_finish_kernel<MODE, true>), dim3(256), dim3(256), 0, st, kp, W, out, cigar, cap);
+    hipLaunchKernelGGL((wf_finish_kernel<MODE, true>), dim3(256), dim3(256), 0, st, kp, W, q, s, out, cigar, cap,
+                       cigar_off);
   } else {
     launch_wf_m<MODE, false>(kp, q, s, W, nw, grouped, p16, st);
-    hipLaunchKernelGGL((wf_finish_kernel<MODE, false>), dim3(256), dim3(256), 0, st, kp, W, out, cigar, cap);
+    hipLaunchKernelGGL((wf_finish_kernel<MODE, false>), dim3(256), dim3(256), 0, st, kp, W, q, s, out, cigar, cap,
+                       cigar_off);
   }
 }
 
@@ -1400,17 +1424,18 @@ WfWs wf_view(void* base_, const WfOffsets& o) {
 
 aln_status_t launch_wf_i32(const KParams& kp, const WfWs& W, const uint8_t* q, const uint8_t* s,
                            aln_result_t* out, int max_waves, bool grouped, bool tb, bool p16, uint32_t* cigar,
-                           int64_t cigar_cap, hipStream_t stream) {
+                           int64_t cigar_cap, hipStream_t stream, const int64_t* cigar_off) {
   hipLaunchKernelGGL(wf_reset_kernel, dim3(256), dim3(256), 0, stream, W);
   switch (kp.mode) {
     case ALN_GLOBAL:
-      launch_wf_mode<ALN_GLOBAL>(kp, q, s, W, max_waves, grouped, tb, p16, out, cigar, cigar_cap, stream);
+      launch_wf_mode<ALN_GLOBAL>(kp, q, s, W, max_waves, grouped, tb, p16, out, cigar, cigar_cap, cigar_off, stream);
       break;
     case ALN_LOCAL:
-      launch_wf_mode<ALN_LOCAL>(kp, q, s, W, max_waves, grouped, tb, p16, out, cigar, cigar_cap, stream);
+      launch_wf_mode<ALN_LOCAL>(kp, q, s, W, max_waves, grouped, tb, p16, out, cigar, cigar_cap, cigar_off, stream);
       break;
     default:
-      launch_wf_mode<ALN_SEMIGLOBAL>(kp, q, s, W, max_waves, grouped, tb, p16, out, cigar, cigar_cap, stream);
+      launch_wf_mode<ALN_SEMIGLOBAL>(kp, q, s, W, max_waves, grouped, tb, p16, out, cigar, cigar_cap, cigar_off,
+                                     stream);
       break;
   }
   return hipGetLastError() == hipSuccess ? ALN_OK : ALN_E_DEVICE;

@@ -106,3 +106,10 @@ def test_wait_limits_host_checks():
 def test_traceback_budget_host_checks():
     assert aln.lib().aln_set_traceback_budget(-1) == -1
     assert aln.lib().aln_set_traceback_budget(0) == 0
+
+
+def test_batch_code_arena_host_checks():
+    """aln_set_batch_code_arena refuses a negative size; 0 restores the default (no device work)."""
+    assert aln.lib().aln_set_batch_code_arena(-1) == -1
+    assert aln.lib().aln_set_batch_code_arena(1 << 20) == 0
+    assert aln.lib().aln_set_batch_code_arena(0) == 0
