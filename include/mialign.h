@@ -126,7 +126,7 @@ aln_status_t aln_batch_workspace_size(const aln_scoring_t* scoring, int64_t n_pa
  * only.  The arena is sized by a bound from max_n, max_m, total_q and total_s; where that bound exceeds
  * the arena budget (aln_set_batch_code_arena, 16 GiB by default) the arena is the budget, pairs take
  * room in the order they reach it, those that find none run one pair per lane, and the lanes' slabs are
- * sized for max_n x max_m (fewer waves in flight, at most 8 GiB of slabs).  Results are identical
+ * sized for max_n x max_m (fewer waves in flight, at most 16 GiB of slabs).  Results are identical
  * either way.
  *   q, s          DEVICE  concatenated uint8 codes of all queries / subjects
  *   q_off, s_off  DEVICE  int64[n_pairs+1]; pair k is q[q_off[k]:q_off[k+1]] vs s[s_off[k]:s_off[k+1]]

@@ -34,7 +34,7 @@ struct KParams {
 
 // Traceback slabs of the one-pair-per-lane kernels hold every cell's code for the waves in flight; a batch
 // of large pairs runs fewer waves rather than asking for more than this.
-constexpr int64_t kTbSlabBudget = (int64_t)8 << 30;
+constexpr int64_t kTbSlabBudget = (int64_t)16 << 30;
 // Codes of the pairs a traceback batch sends to the band wavefront are held in an arena of at most this.
 constexpr int64_t kTbArenaBytes = (int64_t)16 << 30;
 // ... namely every pair of at least kTbMinCells cells or longer than kTbLaneDim on a side.
