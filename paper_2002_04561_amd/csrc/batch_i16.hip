@@ -51,6 +51,34 @@ __device__ __forceinline__ s2 mad_u(s2 a, s2 b, s2 c) {
   const u2 r = __builtin_bit_cast(u2, a) * __builtin_bit_cast(u2, b) + __builtin_bit_cast(u2, c);
   return __builtin_bit_cast(s2, r);
 }
+// The same as one v_pk_mad_u16 where b is a constant: the compiler would otherwise turn a power-of-two
+// b into a shift and an add.
+__device__ __forceinline__ s2 mad_u1(s2 a, s2 b, s2 c) {
+  uint32_t r;
+  asm("v_pk_mad_u16 %0, %1, %2, %3" : "=v"(r) : "v"(bits(a)), "v"(bits(b)), "v"(bits(c)));
+  return from_bits(r);
+}
+// c ? a : b as one v_cndmask on the lane mask of c
+__device__ __forceinline__ uint32_t sel_mask(unsigned long long c, uint32_t a, uint32_t b) {
+  uint32_t r;
+  asm("v_cndmask_b32_e64 %0, %1, %2, %3" : "=v"(r) : "v"(b), "v"(a), "s"(c));
+  return r;
+}
+// x[k] with k given by its bits' lane masks kb[0..]: a tree of v_cndmask (N - 1 of them) instead of a
+// compare and a select per entry
+template <int N>
+__device__ __forceinline__ uint32_t tree_pick(const uint32_t* x, const unsigned long long* kb) {
+  static_assert(N == 4 || N == 8 || N == 16, "row counts of the 16-bit kernel");
+  uint32_t t[N / 2];
+#pragma unroll
+  for (int q = 0; q < N / 2; ++q) t[q] = sel_mask(kb[0], x[2 * q + 1], x[2 * q]);
+#pragma unroll
+  for (int lvl = 1, w = N / 2; w > 1; ++lvl, w /= 2) {
+#pragma unroll
+    for (int q = 0; q < w / 2; ++q) t[q] = sel_mask(kb[lvl], t[2 * q + 1], t[2 * q]);
+  }
+  return t[0];
+}
 
 // LDS query profile of one wave, in 32-bit words.  For letter c, the R scores of a pair slot are
 // W = R/2 words, cut into chunks of CW words (one ds_read_b128, or b64 when R = 4); chunk k of every
@@ -86,8 +114,8 @@ __global__ __launch_bounds__(kI16Block) void batch_i16_kernel(
     const KParams P, const uint8_t* __restrict__ q, const int64_t* __restrict__ q_off, const uint8_t* __restrict__ s,
     const int64_t* __restrict__ s_off, int64_t n_pairs, int64_t max_n, int64_t max_m, aln_result_t* __restrict__ out,
     uint32_t* __restrict__ cigar, const int64_t* __restrict__ cigar_off, char* __restrict__ ws, size_t slab_bytes,
-    size_t rowbuf_bytes, const int* __restrict__ idx, const int* __restrict__ idx_count, int* __restrict__ redo_idx,
-    int* __restrict__ redo_cnt, int* __restrict__ ticket, int force16) {
+    size_t letters_off, size_t dirs_off, const int* __restrict__ idx, const int* __restrict__ idx_count,
+    int* __restrict__ redo_idx, int* __restrict__ redo_cnt, int* __restrict__ ticket, int force16) {
   static_assert(R % 8 == 0 || R == 4, "R must be 4 or a multiple of 8");
   extern __shared__ char smem[];
   int32_t* tab = reinterpret_cast<int32_t*>(smem);
@@ -114,7 +142,11 @@ __global__ __launch_bounds__(kI16Block) void batch_i16_kernel(
   const int64_t wave = (int64_t)blockIdx.x * kI16WavesPerBlock + wib;
   char* slab = ws + wave * slab_bytes;
   uint2* __restrict__ rowbuf = reinterpret_cast<uint2*>(slab);
-  uint32_t* __restrict__ dirs = reinterpret_cast<uint32_t*>(slab + rowbuf_bytes);
+  // the subject letters of the wave's pairs, [column][lane] with pair A's profile index in the low byte
+  // and pair B's in the high one, written once per group: every strip then reads one coalesced row per
+  // column instead of a byte of 128 different subjects
+  uint16_t* __restrict__ letters = reinterpret_cast<uint16_t*>(slab + letters_off);
+  uint32_t* __restrict__ dirs = reinterpret_cast<uint32_t*>(slab + dirs_off);
   constexpr int RW = (R + 3) / 4;  // direction words per column (4 rows x 2 pairs per word)
   const int64_t count = idx ? (int64_t)*idx_count : n_pairs;
   const int64_t groups = (count + 127) / 128;
@@ -154,6 +186,34 @@ __global__ __launch_bounds__(kI16Block) void batch_i16_kernel(
     }
     const int nmax = wave_max_i32(max(nn[0], nn[1])), mmax = wave_max_i32(max(mm[0], mm[1]));
     const int strips = (nmax + R - 1) / R;
+    // Letters of columns 1..mmax (the pad letter P.alphabet past a subject's end), 8 columns per round
+    // so that the byte loads of a round are in flight together.
+    for (int j0 = 1; j0 <= mmax; j0 += 8) {
+      int la[8], lb[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int j = j0 + u;
+        la[u] = j <= mm[0] ? (int)s[sb[0] + j - 1] : -1;
+        lb[u] = j <= mm[1] ? (int)s[sb[1] + j - 1] : -1;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        int ca = P.alphabet, cb = P.alphabet;
+        if (la[u] >= 0) {
+          if (la[u] < P.alphabet)
+            ca = la[u];
+          else
+            bad[0] = true;
+        }
+        if (lb[u] >= 0) {
+          if (lb[u] < P.alphabet)
+            cb = lb[u];
+          else
+            bad[1] = true;
+        }
+        if (j0 + u <= mmax) letters[(size_t)(j0 + u - 1) * 64 + lane] = (uint16_t)(ca | (cb << 8));
+      }
+    }
 
     // optimum bookkeeping per pair (scalars)
     int best[2] = {0, 0}, bi[2] = {0, 0}, bj[2] = {0, 0};
@@ -212,24 +272,19 @@ __global__ __launch_bounds__(kI16Block) void batch_i16_kernel(
       const int rnA = nn[0] - 1 - i0, rnB = nn[1] - 1 - i0;
       const bool lastA = rnA >= 0 && rnA < R, lastB = rnB >= 0 && rnB < R;
       const bool track_last = (MODE == ALN_SEMIGLOBAL) && __any(lastA || lastB);
+      // lane masks of the bits of row n's index in this strip, for each pair
+      constexpr int kRB = R == 16 ? 4 : (R == 8 ? 3 : 2);
+      unsigned long long rbA[kRB], rbB[kRB];
+#pragma unroll
+      for (int b = 0; b < kRB; ++b) {
+        rbA[b] = __builtin_amdgcn_ballot_w64(((rnA >> b) & 1) != 0);
+        rbB[b] = __builtin_amdgcn_ballot_w64(((rnB >> b) & 1) != 0);
+      }
       // Letters and top-row inputs of column j (the pad letter of the profile past a subject's end).
       auto fetch = [&](int j, int& ca, int& cb, uint2& top) {
-        ca = P.alphabet;
-        cb = P.alphabet;
-        if (j <= mm[0]) {
-          const int c = s[sb[0] + j - 1];
-          if (c < P.alphabet)
-            ca = c;
-          else
-            bad[0] = true;
-        }
-        if (j <= mm[1]) {
-          const int c = s[sb[1] + j - 1];
-          if (c < P.alphabet)
-            cb = c;
-          else
-            bad[1] = true;
-        }
+        const uint32_t l2 = j <= mmax ? (uint32_t)letters[(size_t)(j - 1) * 64 + lane] : 0u;
+        ca = j <= mmax ? (int)(l2 & 0xffu) : P.alphabet;
+        cb = j <= mmax ? (int)(l2 >> 8) : P.alphabet;
         if (k == 0)
           top = make_uint2(bits(sp((MODE == ALN_GLOBAL) ? P.go + j * P.ge : 0)), bits(neg2));
         else
@@ -281,8 +336,8 @@ __global__ __launch_bounds__(kI16Block) void batch_i16_kernel(
             if (MODE == ALN_LOCAL) hs = mx(hs, mad_u(subs(one, mn(hv, one)), sp(3), zero));
             s2 nib = hs;
             if (AFFINE) {
-              nib = mad_u(mn(subs(e, tup), one), sp(4), nib);
-              nib = mad_u(mn(subs(ff, tle), one), sp(8), nib);
+              nib = mad_u1(mn(subs(e, tup), one), sp(4), nib);
+              nib = mad_u1(mn(subs(ff, tle), one), sp(8), nib);
             }
             acc[r / 4] |= bits(nib) << (4 * (r & 3));
           }
@@ -303,12 +358,12 @@ __global__ __launch_bounds__(kI16Block) void batch_i16_kernel(
           for (int r = 0; r < R; ++r) cap[r] = from_bits((bits(cap[r]) & ~msk) | (bits(hl[r]) & msk));
         }
         if (track_last) {
-          int va = 0, vb = 0;
+          // row n of each pair, picked by the bits of its index (any row where the pair has none here)
+          uint32_t hw[R];
 #pragma unroll
-          for (int r = 0; r < R; ++r) {
-            if (r == rnA) va = lo16(hl[r]);
-            if (r == rnB) vb = hi16(hl[r]);
-          }
+          for (int r = 0; r < R; ++r) hw[r] = bits(hl[r]);
+          const int va = lo16(from_bits(tree_pick<R>(hw, rbA)));
+          const int vb = hi16(from_bits(tree_pick<R>(hw, rbB)));
           if (lastA && j <= mm[0] && va > brow[0]) {
             brow[0] = va;
             browj[0] = j;
@@ -439,7 +494,8 @@ void launch_i16_t(const KParams& kp, const BatchPlan16& pl, const I16Args& a, hi
   ProfScope prof(TB ? "batch_i16_traceback" : "batch_i16_score", stream);
   hipLaunchKernelGGL((batch_i16_kernel<MODE, AFFINE, TB, R>), dim3(blocks), dim3(kI16Block), lds, stream, kp, a.q,
                      a.q_off, a.s, a.s_off, pl.n_pairs, pl.max_n, pl.max_m, a.out, a.cigar, a.cigar_off,
-                     static_cast<char*>(a.ws), pl.slab_bytes, pl.rowbuf_bytes, a.idx, a.idx_count, a.redo_idx,
+                     static_cast<char*>(a.ws), pl.slab_bytes, pl.rowbuf_bytes, pl.rowbuf_bytes + pl.letters_bytes,
+                     a.idx, a.idx_count, a.redo_idx,
                      a.redo_cnt, a.ticket, a.force16);
 }
 
@@ -491,7 +547,9 @@ aln_status_t plan_batch_i16(const KParams& kp, int64_t n_pairs, int64_t max_n, i
   waves = (waves + kI16WavesPerBlock - 1) / kI16WavesPerBlock * kI16WavesPerBlock;
   pl->n_waves = (int)waves;
   pl->rowbuf_bytes = round256((size_t)(max_m + 1) * 64 * sizeof(uint2));
-  pl->slab_bytes = pl->rowbuf_bytes + (tb ? round256((size_t)strips * RW * (size_t)max_m * 64 * 4) : 0);
+  pl->letters_bytes = round256((size_t)(max_m + 1) * 64 * sizeof(uint16_t));
+  pl->slab_bytes = pl->rowbuf_bytes + pl->letters_bytes +
+                   (tb ? round256((size_t)strips * RW * (size_t)max_m * 64 * 4) : 0);
   if (tb) {
     // fewer waves in flight when every wave's codes would exceed the budget (at least one workgroup)
     const int64_t fit = kTbSlabBudget / (int64_t)pl->slab_bytes / kI16WavesPerBlock * kI16WavesPerBlock;

@@ -135,7 +135,7 @@ struct BatchPlan16 {
   int64_t n_pairs, max_n, max_m;
   int R;
   int n_waves;
-  size_t rowbuf_bytes, slab_bytes, total_bytes;
+  size_t rowbuf_bytes, letters_bytes, slab_bytes, total_bytes;
 };
 struct I16Args {
   const uint8_t* q;
