@@ -58,24 +58,19 @@ __device__ __forceinline__ s2 mad_u1(s2 a, s2 b, s2 c) {
   asm("v_pk_mad_u16 %0, %1, %2, %3" : "=v"(r) : "v"(bits(a)), "v"(bits(b)), "v"(bits(c)));
   return from_bits(r);
 }
-// c ? a : b as one v_cndmask on the lane mask of c
-__device__ __forceinline__ uint32_t sel_mask(unsigned long long c, uint32_t a, uint32_t b) {
-  uint32_t r;
-  asm("v_cndmask_b32_e64 %0, %1, %2, %3" : "=v"(r) : "v"(b), "v"(a), "s"(c));
-  return r;
-}
-// x[k] with k given by its bits' lane masks kb[0..]: a tree of v_cndmask (N - 1 of them) instead of a
-// compare and a select per entry
+// Per 16-bit half, x[k] with k given by its bits: kb[b] holds 0xffff in the half whose index has bit b
+// set.  A tree of N - 1 bit-field inserts (v_bfi_b32) picks both halves' entries at once, instead of a
+// compare and a select per entry and half.
 template <int N>
-__device__ __forceinline__ uint32_t tree_pick(const uint32_t* x, const unsigned long long* kb) {
+__device__ __forceinline__ uint32_t tree_pick(const uint32_t* x, const uint32_t* kb) {
   static_assert(N == 4 || N == 8 || N == 16, "row counts of the 16-bit kernel");
   uint32_t t[N / 2];
 #pragma unroll
-  for (int q = 0; q < N / 2; ++q) t[q] = sel_mask(kb[0], x[2 * q + 1], x[2 * q]);
+  for (int q = 0; q < N / 2; ++q) t[q] = (x[2 * q + 1] & kb[0]) | (x[2 * q] & ~kb[0]);
 #pragma unroll
   for (int lvl = 1, w = N / 2; w > 1; ++lvl, w /= 2) {
 #pragma unroll
-    for (int q = 0; q < w / 2; ++q) t[q] = sel_mask(kb[lvl], t[2 * q + 1], t[2 * q]);
+    for (int q = 0; q < w / 2; ++q) t[q] = (t[2 * q + 1] & kb[lvl]) | (t[2 * q] & ~kb[lvl]);
   }
   return t[0];
 }
@@ -148,6 +143,12 @@ __global__ __launch_bounds__(kI16Block) void batch_i16_kernel(
   uint16_t* __restrict__ letters = reinterpret_cast<uint16_t*>(slab + letters_off);
   uint32_t* __restrict__ dirs = reinterpret_cast<uint32_t*>(slab + dirs_off);
   constexpr int RW = (R + 3) / 4;  // direction words per column (4 rows x 2 pairs per word)
+  // Global and semi-global traceback with 8 or 16 rows per strip store the codes as flags: for each
+  // group of 8 rows a pair of words, the first with "not diagonal" and "not E" and the second with
+  // "E extended" and "F extended", one byte per (flag, pair), bit b for row b of the group.  A flag is
+  // the sign of a packed difference, spread to a byte mask by v_perm's sign selectors and merged with
+  // one and-or: 8 operations per row and step instead of 10.  Same words per column as the nibbles.
+  constexpr bool kFlagCodes = TB && MODE != ALN_LOCAL && R % 8 == 0;
   const int64_t count = idx ? (int64_t)*idx_count : n_pairs;
   const int64_t groups = (count + 127) / 128;
   const s2 ge2 = sp(P.ge), goe2 = sp(P.goe), go2 = sp(P.go), one = sp(1), zero = sp(0);
@@ -272,14 +273,12 @@ __global__ __launch_bounds__(kI16Block) void batch_i16_kernel(
       const int rnA = nn[0] - 1 - i0, rnB = nn[1] - 1 - i0;
       const bool lastA = rnA >= 0 && rnA < R, lastB = rnB >= 0 && rnB < R;
       const bool track_last = (MODE == ALN_SEMIGLOBAL) && __any(lastA || lastB);
-      // lane masks of the bits of row n's index in this strip, for each pair
+      // bits of row n's index in this strip, pair A's in the low half and pair B's in the high half
       constexpr int kRB = R == 16 ? 4 : (R == 8 ? 3 : 2);
-      unsigned long long rbA[kRB], rbB[kRB];
+      uint32_t rnb[kRB];
 #pragma unroll
-      for (int b = 0; b < kRB; ++b) {
-        rbA[b] = __builtin_amdgcn_ballot_w64(((rnA >> b) & 1) != 0);
-        rbB[b] = __builtin_amdgcn_ballot_w64(((rnB >> b) & 1) != 0);
-      }
+      for (int b = 0; b < kRB; ++b)
+        rnb[b] = (((rnA >> b) & 1) ? 0x0000ffffu : 0u) | (((rnB >> b) & 1) ? 0xffff0000u : 0u);
       // Letters and top-row inputs of column j (the pad letter of the profile past a subject's end).
       auto fetch = [&](int j, int& ca, int& cb, uint2& top) {
         const uint32_t l2 = j <= mmax ? (uint32_t)letters[(size_t)(j - 1) * 64 + lane] : 0u;
@@ -329,7 +328,16 @@ __global__ __launch_bounds__(kI16Block) void batch_i16_kernel(
           const s2 ff = AFFINE ? mx(adds(f[r], ge2), tle) : adds(hlo, ge2);
           s2 hv = mx(mx(d, e), ff);
           if (MODE == ALN_LOCAL) hv = mx(hv, zero);
-          if (TB) {
+          if (kFlagCodes) {
+            // words 2g and 2g + 1 of the column hold row group g; byte order (pair A, pair B) per flag
+            const uint32_t bit = 0x01010101u << (r & 7);
+            const uint32_t nd_ne = __builtin_amdgcn_perm(bits(subs(e, hv)), bits(subs(d, hv)), 0x0b0a0908u);
+            acc[2 * (r >> 3)] = (nd_ne & bit) | acc[2 * (r >> 3)];
+            if (AFFINE) {
+              const uint32_t xe_xf = __builtin_amdgcn_perm(bits(subs(tle, ff)), bits(subs(tup, e)), 0x0b0a0908u);
+              acc[2 * (r >> 3) + 1] = (xe_xf & bit) | acc[2 * (r >> 3) + 1];
+            }
+          } else if (TB) {
             const s2 bd = mn(subs(hv, d), one);
             const s2 be = mn(subs(hv, e), one);
             s2 hs = mad_u(bd, be, bd);
@@ -362,8 +370,8 @@ __global__ __launch_bounds__(kI16Block) void batch_i16_kernel(
           uint32_t hw[R];
 #pragma unroll
           for (int r = 0; r < R; ++r) hw[r] = bits(hl[r]);
-          const int va = lo16(from_bits(tree_pick<R>(hw, rbA)));
-          const int vb = hi16(from_bits(tree_pick<R>(hw, rbB)));
+          const s2 hn = from_bits(tree_pick<R>(hw, rnb));
+          const int va = lo16(hn), vb = hi16(hn);
           if (lastA && j <= mm[0] && va > brow[0]) {
             brow[0] = va;
             browj[0] = j;
@@ -374,7 +382,13 @@ __global__ __launch_bounds__(kI16Block) void batch_i16_kernel(
           }
         }
         if (k + 1 < strips) rowbuf[(size_t)j * 64 + lane] = make_uint2(bits(hup), bits(eup));
-        if (TB) {
+        if (kFlagCodes) {
+          uint2* __restrict__ d2 = reinterpret_cast<uint2*>(dirs);
+#pragma unroll
+          for (int g = 0; g < R / 8; ++g)
+            d2[(((size_t)k * (R / 8) + g) * (size_t)max_m + (size_t)(j - 1)) * 64 + lane] =
+                make_uint2(acc[2 * g], acc[2 * g + 1]);
+        } else if (TB) {
 #pragma unroll
           for (int w = 0; w < RW; ++w)
             dirs[(((size_t)k * RW + w) * (size_t)max_m + (size_t)(j - 1)) * 64 + lane] = acc[w];
@@ -471,8 +485,18 @@ __global__ __launch_bounds__(kI16Block) void batch_i16_kernel(
         const int shift = 16 * h;
         auto code = [&](int ii, int jx) -> uint32_t {
           const int kk = (ii - 1) / R, rr = (ii - 1) % R;
-          const uint32_t w = dirs[(((size_t)kk * RW + rr / 4) * (size_t)max_m + (size_t)(jx - 1)) * 64 + lane];
-          return (w >> (shift + 4 * (rr & 3))) & 15u;
+          if constexpr (kFlagCodes) {
+            // the 4-bit code of walk.h from the row's four flags
+            const uint2 w = reinterpret_cast<const uint2*>(
+                dirs)[(((size_t)kk * (R / 8) + (rr >> 3)) * (size_t)max_m + (size_t)(jx - 1)) * 64 + lane];
+            const int sh = 8 * h + (rr & 7);
+            const uint32_t nd = (w.x >> sh) & 1u, ne = (w.x >> (sh + 16)) & 1u;
+            const uint32_t xe = (w.y >> sh) & 1u, xf = (w.y >> (sh + 16)) & 1u;
+            return (nd ? (ne ? 2u : 1u) : 0u) | (xe << 2) | (xf << 3);
+          } else {
+            const uint32_t w = dirs[(((size_t)kk * RW + rr / 4) * (size_t)max_m + (size_t)(jx - 1)) * 64 + lane];
+            return (w >> (shift + 4 * (rr & 3))) & 15u;
+          }
         };
         int qbeg, sbeg, runs;
         walk_back<MODE>(code, ei, ej, cigar + c0, capw, &qbeg, &sbeg, &runs);

@@ -40,7 +40,8 @@ __global__ __launch_bounds__(kBlock) void batch_i32_kernel(
     const KParams P, const uint8_t* __restrict__ q, const int64_t* __restrict__ q_off, const uint8_t* __restrict__ s,
     const int64_t* __restrict__ s_off, int64_t n_pairs, int64_t max_n, int64_t max_m, aln_result_t* __restrict__ out,
     uint32_t* __restrict__ cigar, const int64_t* __restrict__ cigar_off, char* __restrict__ ws, size_t slab_bytes,
-    size_t rowbuf_bytes, const int* __restrict__ idx, const int* __restrict__ idx_count, uint32_t extra_flags,
+    size_t letters_off, size_t dirs_off, const int* __restrict__ idx, const int* __restrict__ idx_count,
+    uint32_t extra_flags,
     int* __restrict__ ticket, const aln_result_t* __restrict__ fwd) {
   constexpr bool TB = TBK != 0;
   constexpr bool FIXED = TBK == 2;
@@ -60,7 +61,10 @@ __global__ __launch_bounds__(kBlock) void batch_i32_kernel(
   const int64_t wave = (int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
   char* slab = ws + wave * slab_bytes;
   int2* __restrict__ rowbuf = reinterpret_cast<int2*>(slab);
-  uint32_t* __restrict__ dirs = reinterpret_cast<uint32_t*>(slab + rowbuf_bytes);
+  // the subject letters of the wave's pairs as table indices, [column][lane], written once per group so
+  // that every strip reads one coalesced row per column instead of a byte of 64 different subjects
+  uint8_t* __restrict__ letters = reinterpret_cast<uint8_t*>(slab + letters_off);
+  uint32_t* __restrict__ dirs = reinterpret_cast<uint32_t*>(slab + dirs_off);
   // pairs come in input order, or from an index list whose length is a device value
   const int64_t count = idx ? (int64_t)*idx_count : n_pairs;
   const int64_t groups = (count + 63) / 64;
@@ -101,6 +105,23 @@ __global__ __launch_bounds__(kBlock) void batch_i32_kernel(
     }
     const int nmax = wave_max_i32(n), mmax = wave_max_i32(m);
     const int strips = (nmax + R - 1) / R;
+    bool bad = false;
+    // letters of columns 1..mmax (kPad past the subject's end), 8 columns per round so that the byte
+    // loads of a round are in flight together
+    for (int j0 = 1; j0 <= mmax; j0 += 8) {
+      int lc[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) lc[u] = j0 + u <= m ? (int)s[sb + j0 + u - 1] : kPad;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        int c = lc[u];
+        if (j0 + u <= m && c >= P.alphabet) {
+          bad = true;
+          c = kPad;
+        }
+        if (j0 + u <= mmax) letters[(size_t)(j0 + u - 1) * 64 + lane] = (uint8_t)c;
+      }
+    }
 
     // optimum bookkeeping
     int32_t best = 0;
@@ -109,7 +130,6 @@ __global__ __launch_bounds__(kBlock) void batch_i32_kernel(
     int32_t brow = 0;                     // semi: best of row n so far, starting at (n, 0)
     int browj = 0;
     int32_t hfinal = 0;                   // global: H(n, m)
-    bool bad = false;
 
     for (int k = 0; k < strips; ++k) {
       const int i0 = k * R;  // this strip holds rows i0+1 .. i0+R
@@ -138,14 +158,7 @@ __global__ __launch_bounds__(kBlock) void batch_i32_kernel(
       const bool has_n = (i0 < n) && (n <= i0 + R);
       const int rn = n - 1 - i0;
       for (int j = 1; j <= mmax; ++j) {
-        int c = kPad;
-        if (j <= m) {
-          c = s[sb + j - 1];
-          if (c >= P.alphabet) {
-            bad = true;
-            c = kPad;
-          }
-        }
+        const int c = letters[(size_t)(j - 1) * 64 + lane];
         int32_t hup, eup;
         if (k == 0) {
           hup = (MODE == ALN_GLOBAL) ? go + j * ge : 0;
@@ -293,13 +306,13 @@ void launch_one(const KParams& kp, const BatchPlan& pl, const uint8_t* q, const 
                 const int64_t* s_off, aln_result_t* out, uint32_t* cigar, const int64_t* cigar_off, void* ws,
                 const int* idx, const int* idx_count, uint32_t extra_flags, int* ticket, const aln_result_t* fwd,
                 hipStream_t stream) {
-  const size_t slab = pl.rowbuf_bytes + pl.dirs_bytes;
+  const size_t slab = pl.rowbuf_bytes + pl.letters_bytes + pl.dirs_bytes;
   const int blocks = (pl.n_waves + kWavesPerBlock - 1) / kWavesPerBlock;
   ProfScope prof(TBK == 2 ? "batch_i32_traceback_from_end" : (TBK ? "batch_i32_traceback" : "batch_i32_score"),
                  stream);
   hipLaunchKernelGGL((batch_i32_kernel<MODE, AFFINE, TBK>), dim3(blocks), dim3(kBlock), 0, stream, kp, q, q_off, s,
                      s_off, pl.n_pairs, pl.max_n, pl.max_m, out, cigar, cigar_off, static_cast<char*>(ws), slab,
-                     pl.rowbuf_bytes, idx, idx_count, extra_flags, ticket, fwd);
+                     pl.rowbuf_bytes, pl.rowbuf_bytes + pl.letters_bytes, idx, idx_count, extra_flags, ticket, fwd);
 }
 
 template <int MODE, bool AFFINE>
@@ -352,14 +365,15 @@ aln_status_t plan_batch_i32(const KParams& kp, int64_t n_pairs, int64_t max_n, i
   waves = (waves + kWavesPerBlock - 1) / kWavesPerBlock * kWavesPerBlock;  // every launched wave owns a slab
   pl.n_waves = (int32_t)waves;
   pl.rowbuf_bytes = round256((size_t)(max_m + 1) * 64 * sizeof(int2));
+  pl.letters_bytes = round256((size_t)(max_m + 1) * 64);
   pl.dirs_bytes = traceback ? round256((size_t)pl.strips * (size_t)max_m * 64 * sizeof(uint32_t)) : 0;
   if (traceback) {
     // fewer waves in flight when every wave's codes would exceed the budget (at least one workgroup)
-    const int64_t slab = (int64_t)(pl.rowbuf_bytes + pl.dirs_bytes);
+    const int64_t slab = (int64_t)(pl.rowbuf_bytes + pl.letters_bytes + pl.dirs_bytes);
     const int64_t fit = kTbSlabBudget / slab / kWavesPerBlock * kWavesPerBlock;
     if (fit < waves) pl.n_waves = (int32_t)(fit > kWavesPerBlock ? fit : kWavesPerBlock);
   }
-  pl.total_bytes = (size_t)pl.n_waves * (pl.rowbuf_bytes + pl.dirs_bytes);
+  pl.total_bytes = (size_t)pl.n_waves * (pl.rowbuf_bytes + pl.letters_bytes + pl.dirs_bytes);
   *plan = pl;
   return ALN_OK;
 }

@@ -51,6 +51,7 @@ struct BatchPlan {
   int32_t strips;       // ceil(max_n / R)
   int32_t n_waves;      // persistent waves of the launch
   size_t rowbuf_bytes;  // per wave
+  size_t letters_bytes; // per wave
   size_t dirs_bytes;    // per wave (traceback only)
   size_t total_bytes;
 };
