@@ -184,6 +184,16 @@ typedef struct {
   int32_t reserved; /* must be zero */
 } aln_batch_config_t;
 
+/* The routing rule aln_align_batch(_ex) applies on the device to a batch of n_pairs pairs with these flags
+ * and config (NULL: the defaults): a pair runs on the band wavefront when n*m >= *min_cells or when n or m
+ * exceeds *max_side, else one pair per lane.  *min_cells = INT64_MAX means never by cells, *max_side =
+ * INT64_MAX no bound on the sides.  Defaults: score-only 2^12 cells, or 2^16 once the batch fills the
+ * per-lane kernels (128 pairs x 8 waves per compute unit); traceback 2^18 cells or a side above 1024,
+ * whatever the config.  Host only (reads the device's compute-unit count).  Returns ALN_E_INVALID for
+ * bad arguments, ALN_E_DEVICE without a device. */
+aln_status_t aln_batch_route(int64_t n_pairs, uint32_t flags, const aln_batch_config_t* config, int64_t* min_cells,
+                             int64_t* max_side);
+
 /* aln_align_batch with explicit execution choices; config == NULL is aln_align_batch.  The
  * workspace size does not depend on the config.  Returns ALN_E_INVALID for a field out of range. */
 aln_status_t aln_align_batch_ex(const aln_scoring_t* scoring, int64_t n_pairs, const uint8_t* q,

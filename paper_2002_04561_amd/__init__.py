@@ -98,6 +98,8 @@ _SIGNATURES = {
     "aln_noalloc_scratch_bytes": (ctypes.c_size_t, []),
     "aln_set_traceback_budget": (ctypes.c_int32, [ctypes.c_int64]),
     "aln_set_batch_code_arena": (ctypes.c_int32, [ctypes.c_int64]),
+    "aln_batch_route": (ctypes.c_int32, [ctypes.c_int64, ctypes.c_uint32, ctypes.c_void_p,
+                                         ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]),
     "aln_traceback_workspace_size": (ctypes.c_int32, [ctypes.POINTER(aln_scoring_t), ctypes.c_int64, ctypes.c_int64,
                                                       ctypes.c_int64, ctypes.POINTER(ctypes.c_size_t)]),
     "aln_traceback": (ctypes.c_int32, [ctypes.POINTER(aln_scoring_t), ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
@@ -334,6 +336,18 @@ def aln_set_traceback_budget(nbytes: int = 0) -> None:
     st = lib().aln_set_traceback_budget(nbytes)
     if st != 0:
         raise AlnError(st, "aln_set_traceback_budget")
+
+
+def aln_batch_route(n_pairs: int, flags: int = SCORE_ONLY, config: Optional["BatchConfig"] = None):
+    """The planner's routing rule for such a batch: (min_cells, max_side); a pair runs on the band
+    wavefront when n*m >= min_cells or n or m > max_side (2**63 - 1: no bound)."""
+    mc, ms = ctypes.c_int64(0), ctypes.c_int64(0)
+    cfg = config.c() if config is not None else None
+    st = lib().aln_batch_route(n_pairs, flags, ctypes.byref(cfg) if cfg is not None else None, ctypes.byref(mc),
+                               ctypes.byref(ms))
+    if st != 0:
+        raise AlnError(st, "aln_batch_route")
+    return int(mc.value), int(ms.value)
 
 
 def aln_set_batch_code_arena(nbytes: int = 0) -> None:

@@ -183,6 +183,17 @@ static bool cfg_valid(const aln_batch_config_t* c) {
   return true;
 }
 
+aln_status_t aln_batch_route(int64_t n_pairs, uint32_t flags, const aln_batch_config_t* config, int64_t* min_cells,
+                             int64_t* max_side) {
+  if (!min_cells || !max_side || n_pairs < 0) return ALN_E_INVALID;
+  if (flags & ~(ALN_TRACEBACK | ALN_FORCE_INT32 | ALN_FORCE_INT16)) return ALN_E_INVALID;
+  if (!cfg_valid(config)) return ALN_E_INVALID;
+  const int cus = device_cu_count();
+  if (cus <= 0) return ALN_E_DEVICE;
+  route_rule(n_pairs, (flags & ALN_TRACEBACK) != 0, resolve_cfg(config), cus, min_cells, max_side);
+  return ALN_OK;
+}
+
 aln_status_t aln_align_batch(const aln_scoring_t* scoring, int64_t n_pairs, const uint8_t* q, const int64_t* q_off,
                              const uint8_t* s, const int64_t* s_off, int64_t max_n, int64_t max_m, int64_t total_q,
                              int64_t total_s, uint32_t flags, aln_result_t* out, uint32_t* cigar,

@@ -279,28 +279,34 @@ BatchCfg resolve_cfg(const aln_batch_config_t* c) {
   return r;
 }
 
-aln_status_t plan_split(int64_t n_pairs, int64_t total_q, int64_t total_s, bool tb, int64_t max_n, int64_t max_m,
-                        const BatchCfg& cfg, SplitPlan* sp) {
-  const int cus = device_cu_count();
-  int64_t min_cells = cfg.wf_min_cells;
+void route_rule(int64_t n_pairs, bool tb, const BatchCfg& cfg, int cus, int64_t* min_cells, int64_t* lane_dim) {
+  int64_t mc = cfg.wf_min_cells;
   if (tb) {
     // Traceback calls send pairs from kTbMinCells cells up to the band wavefront, with their codes in an
     // arena: the one-pair-per-lane kernels hold a code slab per wave for the largest pair they may meet,
     // so such pairs would cost every wave their size.  The rule is fixed, so that the workspace does
     // not depend on the call's configuration.
-    min_cells = kTbMinCells;
-  } else if (min_cells == 0) {
+    mc = kTbMinCells;
+  } else if (mc == 0) {
     // The one-pair-per-lane kernels keep 8 waves of 128 pairs (16-bit lanes) on each compute unit.
     // A batch with fewer pairs leaves waves idle there, and each wave pads its pairs to the largest n
     // and m among them, so such a batch sends its pairs from 2^12 cells up to the band wavefront,
     // whose bands spread over every compute unit.
     const int64_t fill = (int64_t)128 * 8 * (cus > 0 ? cus : 1);
-    min_cells = n_pairs >= fill ? (int64_t)1 << 16 : (int64_t)1 << 12;
+    mc = n_pairs >= fill ? (int64_t)1 << 16 : (int64_t)1 << 12;
   }
+  *min_cells = mc;
+  // A traceback call also sends every pair longer than kTbLaneDim on either side to the wavefront.
+  *lane_dim = tb ? kTbLaneDim : INT64_MAX;
+}
+
+aln_status_t plan_split(int64_t n_pairs, int64_t total_q, int64_t total_s, bool tb, int64_t max_n, int64_t max_m,
+                        const BatchCfg& cfg, SplitPlan* sp) {
+  const int cus = device_cu_count();
+  int64_t min_cells = 0;
+  route_rule(n_pairs, tb, cfg, cus, &min_cells, &sp->lane_dim);
   sp->tb = tb;
   sp->big_cells = min_cells;
-  // A traceback call also sends every pair longer than kTbLaneDim on either side to the wavefront.
-  sp->lane_dim = tb ? kTbLaneDim : INT64_MAX;
   // a traceback walks its pair as given: no transposed pairs
   sp->orient = tb ? 0 : cfg.orient;
   // Code arena of a traceback call.  A wavefront pair takes ceil(n / 256) x 64 x m words, at most

@@ -226,6 +226,9 @@ struct BatchCfg {
 // Process-wide bound on a traceback batch's code arena (default kTbArenaBytes).
 extern int64_t g_tb_arena_bytes;
 BatchCfg resolve_cfg(const aln_batch_config_t* c);
+// The planner's routing rule: a pair runs on the band wavefront when n*m >= *min_cells or n or m >
+// *lane_dim (INT64_MAX: no such bound); cus = the device's compute units.
+void route_rule(int64_t n_pairs, bool tb, const BatchCfg& cfg, int cus, int64_t* min_cells, int64_t* lane_dim);
 aln_status_t plan_split(int64_t n_pairs, int64_t total_q, int64_t total_s, bool tb, int64_t max_n, int64_t max_m,
                         const BatchCfg& cfg, SplitPlan* sp);
 void launch_split(const SplitPlan& sp, int64_t n_pairs, const int64_t* q_off, const int64_t* s_off, int64_t max_n,
