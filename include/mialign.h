@@ -89,7 +89,8 @@ typedef struct {
 #define ALN_SCORE_ONLY 0u
 #define ALN_TRACEBACK 1u   /* aln_align_batch: also write the canonical CIGAR of every pair */
 #define ALN_FORCE_INT32 2u /* skip the packed 16-bit path */
-#define ALN_FORCE_INT16 4u /* test hook: run local pairs in 16 bits even when the a-priori bound fails */
+#define ALN_FORCE_INT16 4u /* accepted, no effect: local pairs run in 16 bits under the saturation check
+                              (best < 32767) whatever the a-priori bound; kept for existing callers */
 #define ALN_LINEAR_SPACE 8u /* aln_align_long with ALN_TRACEBACK: trace back in linear space (checkpoints and
                                tiles relaxed again) even where a code per cell would fit */
 

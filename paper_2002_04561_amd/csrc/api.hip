@@ -263,7 +263,6 @@ aln_status_t aln_align_batch_ex(const aln_scoring_t* scoring, int64_t n_pairs, c
   a.redo_idx = redo_idx;
   a.redo_cnt = redo_cnt;
   a.ticket = ticket16;
-  a.force16 = (flags & ALN_FORCE_INT16) ? 1 : 0;
   st = launch_batch_i16(kp, L.bp16, a, tb, stream);
   if (st != ALN_OK) return st;
   // pairs whose 16-bit range was not provably exact, or that saturated, are recomputed in 32 bits

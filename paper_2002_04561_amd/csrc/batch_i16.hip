@@ -10,11 +10,15 @@
 // merges the two pairs' scores of a row.
 //
 // All arithmetic saturates, so -infinity is -32768 and never wraps.  Exactness:
-// global and semi-global pairs run here only when their score range provably
-// fits (every value lies in [3*go + (n+m)*ge, min(n,m)*max(sigma_max,0)],
-// the 16-bit bound of Sec. IV-A made explicit); local pairs also run when the
-// bound fails, and a pair whose best score reached 32767 may have saturated.
-// Both kinds go to a redo list that the 32-bit kernel recomputes exactly.
+// a global or semi-global pair keeps its 16-bit result only when its score
+// range provably fits (every value lies in [3*go + (n+m)*ge,
+// min(n,m)*max(sigma_max,0)], the 16-bit bound of Sec. IV-A made explicit);
+// otherwise it goes to a redo list that the 32-bit kernel recomputes exactly.
+// A local pair keeps its result whenever its best score stayed below 32767,
+// whatever the bound says: every H is then below 32767 and at least 0, so no H
+// saturated, and a value clamped at -32768 (an E or F far below 0) loses every
+// maximum it enters, as its true value would.  A local pair that reached 32767
+// may have saturated and is redone.
 #include "internal.h"
 #include "walk.h"
 
@@ -110,7 +114,7 @@ __global__ __launch_bounds__(kI16Block) void batch_i16_kernel(
     const int64_t* __restrict__ s_off, int64_t n_pairs, int64_t max_n, int64_t max_m, aln_result_t* __restrict__ out,
     uint32_t* __restrict__ cigar, const int64_t* __restrict__ cigar_off, char* __restrict__ ws, size_t slab_bytes,
     size_t letters_off, size_t dirs_off, const int* __restrict__ idx, const int* __restrict__ idx_count,
-    int* __restrict__ redo_idx, int* __restrict__ redo_cnt, int* __restrict__ ticket, int force16) {
+    int* __restrict__ redo_idx, int* __restrict__ redo_cnt, int* __restrict__ ticket) {
   static_assert(R % 8 == 0 || R == 4, "R must be 4 or a multiple of 8");
   extern __shared__ char smem[];
   int32_t* tab = reinterpret_cast<int32_t*>(smem);
@@ -181,7 +185,7 @@ __global__ __launch_bounds__(kI16Block) void batch_i16_kernel(
           nn[h] = (int)a;
           mm[h] = (int)b;
           const bool f = fits16(P, nn[h], mm[h]);
-          ok16[h] = f || (MODE == ALN_LOCAL && force16 && mm[h] < 32767);
+          ok16[h] = f || (MODE == ALN_LOCAL && mm[h] < 32767);
         }
       }
     }
@@ -520,7 +524,7 @@ void launch_i16_t(const KParams& kp, const BatchPlan16& pl, const I16Args& a, hi
                      a.q_off, a.s, a.s_off, pl.n_pairs, pl.max_n, pl.max_m, a.out, a.cigar, a.cigar_off,
                      static_cast<char*>(a.ws), pl.slab_bytes, pl.rowbuf_bytes, pl.rowbuf_bytes + pl.letters_bytes,
                      a.idx, a.idx_count, a.redo_idx,
-                     a.redo_cnt, a.ticket, a.force16);
+                     a.redo_cnt, a.ticket);
 }
 
 template <int MODE, bool AFFINE, bool TB>

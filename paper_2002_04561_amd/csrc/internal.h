@@ -152,7 +152,6 @@ struct I16Args {
   int* redo_idx;
   int* redo_cnt;
   int* ticket;  // group dispenser, zero before the launch
-  int force16;
 };
 aln_status_t plan_batch_i16(const KParams& kp, int64_t n_pairs, int64_t max_n, int64_t max_m, bool tb,
                             BatchPlan16* plan);

@@ -339,3 +339,43 @@ def test_understated_totals_flag_wavefront_pairs(gpu):
         else:
             assert (res["score"][k], res["q_end"][k], res["s_end"][k]) == (ores["score"][k], ores["q_end"][k],
                                                                           ores["s_end"][k]), k
+
+
+@pytest.mark.parametrize("tb", [False, True], ids=["score", "traceback"])
+def test_local_int16_beyond_the_bound(gpu, tb):
+    """Unrelated protein pairs whose min(n, m) x max sigma exceeds the 16-bit a-priori bound, but whose local
+    optima stay far below 32767, keep their 16-bit results (no ALN_RES_INT32_REDO) and equal the oracle's bit
+    for bit; two identical pairs reach 32767 and are redone in 32 bits.  Score-only: 3300..4000 letters under
+    the +4..+11 table, identical pairs of 5200.  Traceback (whose lanes take pairs under 2^18 cells): 400..500
+    letters under the same table with a diagonal of +100, identical pairs of 500."""
+    import paper_2002_04561_amd as aln
+    rng = np.random.default_rng(41)
+    sig = synth.protein_sigma(rng)
+    lo, hi, hot = (3300, 4000, 5200) if not tb else (400, 500, 500)
+    if tb:
+        sig = sig.copy()
+        np.fill_diagonal(sig, 100)
+    qs, ss = [], []
+    for k in range(48):
+        n, m = int(rng.integers(lo, hi)), int(rng.integers(lo, hi))
+        qs.append(rng.integers(0, 20, n, dtype=np.uint8))
+        ss.append(rng.integers(0, 20, m, dtype=np.uint8))
+    for _ in range(2):
+        a = rng.integers(0, 20, hot, dtype=np.uint8)
+        qs.append(a)
+        ss.append(a.copy())
+    q, qo = synth.pack(qs)
+    s, so = synth.pack(ss)
+    w = synth.Workload("local16", synth.LOCAL, 20, -11, -1, q, qo, s, so, subst=sig, traceback=tb)
+    n, m = w.lengths()
+    assert (np.minimum(n, m) * int(sig.max()) > 32000).all()  # the a-priori bound fails for every pair
+    assert tb is False or (n * m < (1 << 18)).all()
+    ores, ocig = run_oracle(w, tb)
+    assert (ores["score"][-2:] > 32767).all() and (ores["score"][:-2] < 32767).all()
+    lanes_only = aln.BatchConfig(wf_min_cells=-1)
+    flags = aln.TRACEBACK if tb else aln.SCORE_ONLY
+    gres, gcig = run_gpu(w, flags, config=lanes_only)
+    bad = compare(w, gres, gcig, ores, ocig, "local16")
+    assert not bad, "\n".join(bad[:10])
+    redo = (gres["flags"] & aln.RES_INT32_REDO) != 0
+    assert not redo[:-2].any() and redo[-2:].all()
