@@ -169,12 +169,12 @@ aln_status_t aln_align_batch(const aln_scoring_t* scoring, int64_t n_pairs, cons
  *                    fewer than 16 bands per compute unit (estimated from total_q + total_s), else 1.
  *                    aln_align_long always uses 4.
  *   wf_bits          wavefront engine, grouped bands of score-only local alignments over alphabets
- *                    of up to 4 letters: 16 => packed 16-bit cells (two half bands per lane, scores
+ *                    of up to 32 letters: 16 => packed 16-bit cells (two half bands per lane, scores
  *                    relative to per-block offsets) where the scores' step bound keeps them exact
  *                    (max|sigma| + |gap_open| + 2 |gap_extend| <= 32), else 32-bit lanes; 32 =>
- *                    32-bit lanes only.  0 => 32.  Results are identical either way; with one wave
- *                    per SIMD the packed cells' longer dependent latency leaves them slower on
- *                    MI355X, so aln_align_long uses 32. */
+ *                    32-bit lanes only.  0 => 32.  Results are identical either way; the packed
+ *                    cells are slower on MI355X (one long pair and the uneven protein batch alike),
+ *                    so aln_align_long uses 32. */
 typedef struct {
   int64_t wf_min_cells;
   int32_t wf_waves_per_cu;

@@ -84,7 +84,8 @@ __device__ __forceinline__ int lane_select(bool c, int a, int b) {
   return r;
 }
 
-// Packed 16-bit bands (local alignment, score only, alphabets of up to 4 letters).  A 32-bit lane
+// Packed 16-bit bands (local alignment, score only; register profiles for up to 4 letters, per-lane LDS
+// profiles of two 16-bit rows per half for up to 32).  A 32-bit lane
 // register holds two 16-bit cells: rows of the band's upper half (HB = 128 rows) in its low half and
 // rows of the lower half in its high half, the lower half running kP16Delay steps behind so that the
 // two are independent within a step -- the two halves are independent submatrices sharing one vector
@@ -450,7 +451,8 @@ __global__ __launch_bounds__(kWfBlock) void wf_i32_group_kernel(const KParams P,
   __shared__ long long s_t0;                 // first item of the group
   __shared__ int s_err;
   extern __shared__ uint32_t lprof[];        // kProfLane: [wave][letter][lane], alphabet letters
-  static_assert(!P16 || (MODE == ALN_LOCAL && PROF == kProfReg && !TB && R == 4), "packed bands: local, score only");
+  static_assert(!P16 || (MODE == ALN_LOCAL && (PROF == kProfReg || PROF == kProfLane) && !TB && R == 4),
+                "packed bands: local, score only, register or per-lane profiles");
   static_assert(!CKPT || (!TB && !P16 && R == 4), "checkpoints: 32-bit score-only bands");
   // packed bands: the upper half's bottom row (absolute H, E) on its way to the lower half
   __shared__ int2 dline[P16 ? kWfWavesPerBlock : 1][P16 ? kDelayRing : 1];
@@ -598,6 +600,7 @@ __global__ __launch_bounds__(kWfBlock) void wf_i32_group_kernel(const KParams P,
     const int i0 = b * BH;
     // half h (0 upper, 1 lower), row r (0, 1): i = i0 + h * HB + 2 lane + r + 1
     int prof[2][2];
+    int rowc[2][2];
     int32_t nuA[2][2], bvA[2][2];
     int bjA[2][2];
     bool bad = false;
@@ -614,16 +617,38 @@ __global__ __launch_bounds__(kWfBlock) void wf_i32_group_kernel(const KParams P,
             c = kPad;
           }
         }
+        rowc[h][r] = c;
         uint32_t w = 0;
-        for (int a = 0; a < 4; ++a) {
-          const int v = (c < P.alphabet && a < P.alphabet) ? sig_rc(c, a) : -128;
-          w |= ((uint32_t)(v & 0xff)) << (8 * a);
+        if (PROF == kProfReg) {
+          for (int a = 0; a < 4; ++a) {
+            const int v = (c < P.alphabet && a < P.alphabet) ? sig_rc(c, a) : -128;
+            w |= ((uint32_t)(v & 0xff)) << (8 * a);
+          }
         }
         prof[h][r] = (int)w;
         nuA[h][r] = -i * ge;  // Hb(i, j) of H = 0, also Hb(i, 0)
         bvA[h][r] = kNeg32;
         bjA[h][r] = 0;
       }
+    // kProfLane: per column letter, this lane's two rows of each half as 16-bit sigma - ge, the upper
+    // half's in lpu[letter * 64] and the lower half's in lpl[letter * 64]; each lane reads only its own
+    // words, so no barrier
+    const uint32_t* __restrict__ lpu = lprof + (PROF == kProfLane ? (size_t)wib * 2 * P.alphabet * 64 + lane : 0);
+    const uint32_t* __restrict__ lpl = lpu + (PROF == kProfLane ? (size_t)P.alphabet * 64 : 0);
+    if (PROF == kProfLane) {
+      uint32_t* wu = lprof + (size_t)wib * 2 * P.alphabet * 64 + lane;
+      for (int a = 0; a < P.alphabet; ++a) {
+        uint32_t hw[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int v0 = rowc[h][0] < P.alphabet ? sig_rc(rowc[h][0], a) : -128;
+          const int v1 = rowc[h][1] < P.alphabet ? sig_rc(rowc[h][1], a) : -128;
+          hw[h] = (uint32_t)(v0 & 0xffff) | ((uint32_t)v1 << 16);
+        }
+        wu[a * 64] = hw[0];
+        wu[(P.alphabet + a) * 64] = hw[1];
+      }
+    }
     int32_t B0 = -i0 * ge, B1 = -(i0 + HB) * ge;  // offsets: Hb of each half's top row at column 0
     int hl[2], f[2], nu[2], bvr[2];
 #pragma unroll
@@ -648,7 +673,7 @@ __global__ __launch_bounds__(kWfBlock) void wf_i32_group_kernel(const KParams P,
         bad = true;
         c = 0;
       }
-      return c * 8;
+      return PROF == kProfLane ? c * 64 : c * 8;
     };
     int cn0 = lane < BLK ? letter_raw(1 + lane) : -1;
     int cn1 = lane < BLK ? letter_raw(1 + lane - D) : -1;
@@ -729,6 +754,8 @@ __global__ __launch_bounds__(kWfBlock) void wf_i32_group_kernel(const KParams P,
         const int in_c = dpp_shr1(in_top_c, cur_c);
         cur_c = in_c;
         const int c1s = (int)((uint32_t)in_c >> 16);
+        const uint32_t wu = PROF == kProfLane ? lpu[in_c & 0xffff] : 0u;
+        const uint32_t wl = PROF == kProfLane ? lpl[c1s] : 0u;
         const bool ok0 = !CK || (j0 >= 1 && j0 <= m), ok1 = !CK || (j1 >= 1 && j1 <= m);
         const int keep = (ok0 ? 0 : 0xffff) | (ok1 ? 0 : (int)0xffff0000u);  // bits left unchanged
         auto sel = [&](int old, int nw) { return CK ? ((keep & old) | (~keep & nw)) : nw; };
@@ -738,9 +765,15 @@ __global__ __launch_bounds__(kWfBlock) void wf_i32_group_kernel(const KParams P,
           const int hlo = hl[r];
           const int e = AFFINE ? pmax(eup, padd(hup, go2)) : hup;
           const int ff = AFFINE ? pmax(padd(f[r], ge2), padd(hlo, goe2)) : padd(hlo, ge2);
-          // sigma - ge of both halves' cells: the low bytes of two bit-field extracts, side by side
-          const int sg = (int)__builtin_amdgcn_perm((uint32_t)__builtin_amdgcn_sbfe(prof[1][r], c1s, 8),
-                                                    (uint32_t)__builtin_amdgcn_sbfe(prof[0][r], in_c, 8), 0x05040100u);
+          // sigma - ge of both halves' cells side by side: register bytes picked by bit-field extracts
+          // (kProfReg), or the 16-bit halves of the two halves' profile words (kProfLane)
+          int sg;
+          if constexpr (PROF == kProfLane) {
+            sg = (int)__builtin_amdgcn_perm(wl, wu, r ? 0x07060302u : 0x05040100u);
+          } else {
+            sg = (int)__builtin_amdgcn_perm((uint32_t)__builtin_amdgcn_sbfe(prof[1][r], c1s, 8),
+                                            (uint32_t)__builtin_amdgcn_sbfe(prof[0][r], in_c, 8), 0x05040100u);
+          }
           const int d = padd(hd, sg);
           const int h = pmax(pmax(d, pmax(e, ff)), nu[r]);
           if (CK) {
@@ -1317,11 +1350,12 @@ void launch_wf_t(const KParams& kp, const uint8_t* q, const uint8_t* s, const Wf
                  bool p16, hipStream_t stream) {
   const int blocks = (n_waves + kWfWavesPerBlock - 1) / kWfWavesPerBlock;
   const size_t lds = PROF == kProfLane ? (size_t)kWfWavesPerBlock * kp.alphabet * 64 * sizeof(uint32_t) : 0;
-  constexpr bool kCanPack = MODE == ALN_LOCAL && PROF == kProfReg && !TB;
+  constexpr bool kCanPack = MODE == ALN_LOCAL && (PROF == kProfReg || PROF == kProfLane) && !TB;
   if (kCanPack && grouped && p16 && p16_exact(kp)) {
+    // packed bands keep two 16-bit rows of each half per letter and lane: twice the words
     ProfScope prof("wavefront_p16", stream);
     hipLaunchKernelGGL((wf_i32_group_kernel<MODE, AFFINE, PROF, TB, kWfR, kCanPack, false>), dim3(blocks),
-                       dim3(kWfBlock), lds, stream, kp, q, s, W);
+                       dim3(kWfBlock), 2 * lds, stream, kp, q, s, W);
     return;
   }
   if (!TB && W.ckcols) {
@@ -1346,7 +1380,7 @@ void launch_wf_p(const KParams& kp, const uint8_t* q, const uint8_t* s, const Wf
   if (bytes && kp.alphabet <= 4)
     launch_wf_t<MODE, AFFINE, kProfReg, TB>(kp, q, s, W, nw, grouped, p16, st);
   else if (bytes)
-    launch_wf_t<MODE, AFFINE, kProfLane, TB>(kp, q, s, W, nw, grouped, false, st);
+    launch_wf_t<MODE, AFFINE, kProfLane, TB>(kp, q, s, W, nw, grouped, p16, st);
   else
     launch_wf_t<MODE, AFFINE, kProfTable, TB>(kp, q, s, W, nw, grouped, false, st);
 }

@@ -299,6 +299,48 @@ def test_wavefront_packed16(gpu, scheme, orient):
         assert np.array_equal(gres[f], g32[f]), f
 
 
+@pytest.mark.parametrize("diag", [None, 19, 21], ids=["protein", "at_bound", "beyond_bound"])
+@pytest.mark.parametrize("orient", [1, -1], ids=["oriented", "as_given"])
+def test_wavefront_packed16_protein(gpu, diag, orient):
+    """Packed 16-bit bands with per-lane 20-letter profiles (local affine -11/-1): the protein table (+4..+11 on
+    the diagonal), one with +19 (step bound max|sigma| + |go| + 2|ge| = 32, the largest the packed bands
+    take) and one with +21 (beyond it: wf_bits = 16 falls back to 32-bit bands), against the oracle and the
+    32-bit bands; related pairs long enough that the optimum passes 32,767, short, multi-band and unrelated
+    pairs."""
+    import paper_2002_04561_amd as aln
+    rng = np.random.default_rng(7300 + (diag or 0) + (orient > 0))
+    sig = synth.protein_sigma(rng)
+    if diag is not None:
+        sig = sig.copy()
+        np.fill_diagonal(sig, diag)
+    lens = [(6000, 5800), (5800, 6000), (100, 900), (129, 700), (256, 256), (257, 600), (1, 500), (500, 1),
+            (127, 128), (640, 3000)]
+    lens += [tuple(int(x) for x in rng.integers(1, 2500, 2)) for _ in range(16)]
+    qs, ss = [], []
+    for k, (a, b) in enumerate(lens):
+        x = rng.integers(0, 20, a, dtype=np.uint8)
+        if k % 3 != 2:
+            y = synth.mutate_geometric(rng, x, 0.04, 0.01, 2.0, 20)[:b]
+            if len(y) < b:
+                y = np.concatenate([y, rng.integers(0, 20, b - len(y), dtype=np.uint8)])
+        else:
+            y = rng.integers(0, 20, b, dtype=np.uint8)
+        qs.append(x)
+        ss.append(y)
+    q, qo = synth.pack(qs)
+    s, so = synth.pack(ss)
+    w = synth.Workload("packed16_protein", synth.LOCAL, 20, -11, -1, q, qo, s, so, subst=sig)
+    cfg = dict(wf_min_cells=1, wf_orient=orient, wf_group=4)
+    gres, _ = run_gpu(w, aln.SCORE_ONLY, config=aln.BatchConfig(wf_bits=16, **cfg))
+    ores, _ = run_oracle(w, False)
+    bad = compare(w, gres, None, ores, None, "p16 protein/%s/%d" % (diag, orient))
+    assert not bad, "\n".join(bad[:10])
+    assert int(ores["score"][0]) > 32767  # the first pair's optimum does not fit 16 bits
+    g32, _ = run_gpu(w, aln.SCORE_ONLY, config=aln.BatchConfig(wf_bits=32, **cfg))
+    for f in ("score", "q_end", "s_end", "flags"):
+        assert np.array_equal(gres[f], g32[f]), f
+
+
 @pytest.mark.parametrize("waves", [1, 4, 16, 32])
 @pytest.mark.parametrize("group", [1, 4], ids=["alone", "grouped"])
 def test_wavefront_waves_per_cu(gpu, waves, group):
