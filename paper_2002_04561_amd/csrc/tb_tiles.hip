@@ -5,10 +5,13 @@
 // checkpoints: the bottom row (H, E) of every workgroup of 4 bands (every kTileRows rows) and the column
 // (H, F) of every kTileCols-th column, all rows.  Any tile of kTileRows x kTileCols cells can then be
 // relaxed again on its own from the row above it and the column left of it, replaying exactly the
-// forward pass's integers.  The walk goes back through segments of rows, bottom first: for each
-// segment, every tile left of the walk's column and at or above its row is relaxed again in parallel
-// (one workgroup of 4 band waves per tile), storing the 4-bit predecessor codes of walk.h for the
-// segment only; then one wave walks the segment (walk_wave.h) and hands its position to the next
+// forward pass's integers.  The walk goes back through segments of rows, bottom first.  For each
+// segment, the tiles at or above the walk's row and left of its column, within a window as wide as the
+// rows the walk has left in the segment plus kTbWinMargin columns, are relaxed again in parallel (one
+// workgroup of 4 band waves per tile), storing the 4-bit predecessor codes of walk.h for the segment
+// only; then one wave walks the segment (walk_wave.h).  A near-diagonal path crosses the segment inside
+// the window; a walk that reaches the window's left edge first stops there, the tiles left of the
+// window are relaxed again, and the walk goes on.  The walk then hands its position to the next
 // segment up.  Each cell is relaxed again at most once, so the whole traceback relaxes at most twice
 // the cells of the matrix; memory is one segment of codes plus the checkpoints, not a code per cell.
 #include "band.h"
@@ -21,6 +24,7 @@ namespace {
 constexpr int kTBlk = 32;      // steps between lane-0 input refills
 constexpr int kTRing = 256;    // columns held by the ring between two bands of a tile
 constexpr int kTWaves = kTileRows / kWfBand;  // bands (waves) of a tile
+constexpr int kTbWinMargin = 2 * kTileCols;   // window columns beyond the rows the walk has left
 
 // Profile kinds of the band wavefront (band.h): register bytes for up to 4 letters, else the LDS table.
 
@@ -41,13 +45,24 @@ struct TbView {
   uint16_t* codes;     // the current segment's codes: [row group][column - 1], stride m
   WalkState* walk;
   int* error;          // set when a bounded wait gives up
+  int* win_lo;         // the current segment's window: its first tile column
 };
+
+// First tile column of the window of a segment whose tiles are relaxed again from the walk at (i, j):
+// the walk's column minus the rows it has left in the segment and a margin.
+__device__ __forceinline__ int tb_window_lo(int i, int j, int seg_r0) {
+  const int c = j - (i - seg_r0) - kTbWinMargin;
+  return c > 0 ? c / kTileCols : 0;
+}
 
 // One tile of the segment `seg`, relaxed again with the codes stored.  Values carry the row bias of
 // the band wavefront (Hb = H - i*ge, likewise E and F), so they are the forward pass's own integers.
+// Phase 0 relaxes the tiles of the window, phase 1 (after a walk that stopped at the window's left
+// edge) those left of it.
 template <int MODE, bool AFFINE, int PROF>
 __global__ __launch_bounds__(64 * kTWaves) void tb_tile_kernel(const KParams P, const uint8_t* __restrict__ Q,
-                                                              const uint8_t* __restrict__ S, TbView V, int seg) {
+                                                              const uint8_t* __restrict__ S, TbView V, int seg,
+                                                              int phase) {
   constexpr int R = kWfR, BLK = kTBlk;
   __shared__ int32_t tab[kTab * kTab];
   __shared__ int4 stage[kTWaves][3][BLK / 4];  // lane-0 inputs of BLK steps: H, E, letter
@@ -70,8 +85,11 @@ __global__ __launch_bounds__(64 * kTWaves) void tb_tile_kernel(const KParams P, 
   const int seg_r0 = seg * V.seg_rows;
   const int tr = blockIdx.x / V.strips, sc = blockIdx.x % V.strips;
   const int R0 = seg_r0 + tr * kTileRows, C0 = sc * kTileCols;
-  // only tiles at or above the walk's row and left of its column, in the segment it is in
+  // only tiles at or above the walk's row and left of its column, in the segment it is in, and in
+  // (phase 0) or left of (phase 1) the segment's window
   if (w_done || i_w <= seg_r0 || R0 >= i_w || C0 >= j_w) return;
+  const int lo = phase == 0 ? tb_window_lo(i_w, j_w, seg_r0) : *V.win_lo;
+  if (phase == 0 ? sc < lo : sc >= lo) return;
   const int rows_hi = min(n, i_w);
   const int cols = min(C0 + kTileCols, j_w) - C0;  // tile columns C0+1 .. C0+cols
   const int i0 = R0 + wib * kWfBand;               // this band's rows i0+1 .. i0+kWfBand
@@ -249,15 +267,23 @@ __global__ __launch_bounds__(64 * kTWaves) void tb_tile_kernel(const KParams P, 
   }
 }
 
-// One wave walks the codes of segment `seg` from where the walk stands, if it stands in it.
+// One wave walks the codes of segment `seg` from where the walk stands, if it stands in it: in phase 0
+// up to the window's left edge (recorded for phase 1's tiles), in phase 1 on from there.
 template <int MODE>
-__global__ __launch_bounds__(64) void tb_walk_kernel(TbView V, int seg, uint32_t* __restrict__ cig, int64_t cap) {
+__global__ __launch_bounds__(64) void tb_walk_kernel(TbView V, int seg, int phase, uint32_t* __restrict__ cig,
+                                                     int64_t cap) {
   __shared__ uint16_t win[kWalkGroups * kWalkCols];
   const int lane = threadIdx.x;
   WalkState S = *V.walk;
   const int seg_r0 = seg * V.seg_rows;
   if (S.done || S.i <= seg_r0) return;
-  walk_core<MODE>(V.codes, V.m, seg_r0, S, win, lane, cig, cap);
+  int cb = 0;
+  if (phase == 0) {
+    const int lo = tb_window_lo(S.i, S.j, seg_r0);
+    cb = lo * kTileCols;
+    if (lane == 0) *V.win_lo = lo;
+  }
+  walk_core<MODE>(V.codes, V.m, seg_r0, cb, S, win, lane, cig, cap);
   __syncthreads();  // every lane has read the state before lane 0 writes it
   if (lane == 0) *V.walk = S;
 }
@@ -275,7 +301,7 @@ __global__ __launch_bounds__(64) void tb_init_kernel(const aln_result_t* __restr
   if (r.flags) {
     S.done = 1;  // no CIGAR for a failed forward pass
   } else if (r.q_end == 0 || r.s_end == 0) {
-    walk_core<MODE>(nullptr, 0, 0, S, win, lane, cig, cap);
+    walk_core<MODE>(nullptr, 0, 0, 0, S, win, lane, cig, cap);
   }
   if (lane == 0) {
     *V.walk = S;
@@ -305,11 +331,11 @@ __global__ __launch_bounds__(64) void tb_final_kernel(aln_result_t* __restrict__
 }
 
 template <int MODE, bool AFFINE, int PROF>
-void launch_tiles(const KParams& kp, const uint8_t* q, const uint8_t* s, const TbView& V, int seg,
+void launch_tiles(const KParams& kp, const uint8_t* q, const uint8_t* s, const TbView& V, int seg, int phase,
                   hipStream_t stream) {
   const int tiles = V.seg_rows / kTileRows * V.strips;
   hipLaunchKernelGGL((tb_tile_kernel<MODE, AFFINE, PROF>), dim3(tiles), dim3(64 * kTWaves), 0, stream, kp, q, s, V,
-                     seg);
+                     seg, phase);
 }
 
 template <int MODE>
@@ -318,22 +344,24 @@ void launch_rounds(const KParams& kp, const uint8_t* q, const uint8_t* s, const 
   hipLaunchKernelGGL((tb_init_kernel<MODE>), dim3(1), dim3(64), 0, stream, out, V, cigar, cap);
   const bool bytes = kp.sigma_max - kp.ge <= 127 && kp.sigma_min - kp.ge >= -127;
   for (int seg = nseg - 1; seg >= 0; --seg) {
-    {
-      ProfScope prof("traceback_tiles", stream);
-      if (kp.go != 0) {
-        if (bytes && kp.alphabet <= 4)
-          launch_tiles<MODE, true, kProfReg>(kp, q, s, V, seg, stream);
-        else
-          launch_tiles<MODE, true, kProfTable>(kp, q, s, V, seg, stream);
-      } else {
-        if (bytes && kp.alphabet <= 4)
-          launch_tiles<MODE, false, kProfReg>(kp, q, s, V, seg, stream);
-        else
-          launch_tiles<MODE, false, kProfTable>(kp, q, s, V, seg, stream);
+    for (int phase = 0; phase < 2; ++phase) {
+      {
+        ProfScope prof("traceback_tiles", stream);
+        if (kp.go != 0) {
+          if (bytes && kp.alphabet <= 4)
+            launch_tiles<MODE, true, kProfReg>(kp, q, s, V, seg, phase, stream);
+          else
+            launch_tiles<MODE, true, kProfTable>(kp, q, s, V, seg, phase, stream);
+        } else {
+          if (bytes && kp.alphabet <= 4)
+            launch_tiles<MODE, false, kProfReg>(kp, q, s, V, seg, phase, stream);
+          else
+            launch_tiles<MODE, false, kProfTable>(kp, q, s, V, seg, phase, stream);
+        }
       }
+      ProfScope prof("traceback_walk", stream);
+      hipLaunchKernelGGL((tb_walk_kernel<MODE>), dim3(1), dim3(64), 0, stream, V, seg, phase, cigar, cap);
     }
-    ProfScope prof("traceback_walk", stream);
-    hipLaunchKernelGGL((tb_walk_kernel<MODE>), dim3(1), dim3(64), 0, stream, V, seg, cigar, cap);
   }
   hipLaunchKernelGGL(tb_final_kernel, dim3(1), dim3(64), 0, stream, out, V, cigar, cap);
 }
@@ -361,7 +389,10 @@ aln_status_t plan_long_ls(int64_t n, int64_t m, int64_t code_budget, LongLsPlan*
   const int64_t ncols = pl->strips > 0 ? pl->strips - 1 : 0;
   pl->off_ckcols = off;
   off += a256((size_t)ncols * (size_t)pl->ck_ld * sizeof(int2));
-  // rows per segment: as many tile rows as the code budget allows, at least one
+  // rows per segment: as many tile rows as the code budget allows, at least one.  A segment's window
+  // is about as wide as its rows, so shorter segments would relax fewer cells, but a tile takes its
+  // 2048 steps whatever the number of tiles beside it: taller segments keep more tiles in flight per
+  // launch (at 262144^2, segments of 8192 rows took 48.8 ms of tiles per traceback, of 32768 rows 20.1)
   const int64_t rows_all = groups * kTileRows;
   int64_t seg = m > 0 ? code_budget * 2 / m / kTileRows * kTileRows : rows_all;
   if (seg < kTileRows) seg = kTileRows;
@@ -398,6 +429,7 @@ aln_status_t launch_long_ls(const KParams& kp, const LongLsPlan& pl, const uint8
   V.codes = reinterpret_cast<uint16_t*>(base + pl.off_codes);
   V.walk = reinterpret_cast<WalkState*>(base + pl.off_walk);
   V.error = reinterpret_cast<int*>(base + pl.off_walk + 128);
+  V.win_lo = reinterpret_cast<int*>(base + pl.off_walk + 192);
   switch (kp.mode) {
     case ALN_GLOBAL:
       launch_rounds<ALN_GLOBAL>(kp, q, s, V, pl.nseg, out, cigar, cigar_cap, stream);

@@ -12,7 +12,9 @@
 // The codes may cover only a segment of rows, r0 + 1 .. r0 + rows: the walk then stops when it
 // reaches row r0 (in the no-gap state or inside a vertical gap), and a later call with the segment
 // above continues it.  This is the linear-space traceback of AnySeq Sec. III-A: the segments are
-// relaxed again one at a time from stored rows, so only one segment's codes are held at once.
+// relaxed again one at a time from stored rows, so only one segment's codes are held at once.  They
+// may also cover only the columns right of cb: the walk then stops when it reaches column cb, and a
+// later call with the columns left of it continues.
 #pragma once
 #include "internal.h"
 
@@ -45,10 +47,11 @@ __device__ __forceinline__ void walk_start(WalkState& S, int i, int j) {
   S.pad_ = 0;
 }
 
-// Walks from S through the codes of rows r0 + 1 .. (row group g of the segment, column c at
-// codes[g * ld + c - 1]).  Returns when the walk is done or has reached row r0 > 0.
+// Walks from S through the codes of rows r0 + 1 .. and columns cb + 1 .. (row group g of the segment,
+// column c at codes[g * ld + c - 1]).  Returns when the walk is done or has reached row r0 > 0 or
+// column cb > 0.
 template <int MODE>
-__device__ void walk_core(const uint16_t* __restrict__ codes, int64_t ld, int r0, WalkState& S,
+__device__ void walk_core(const uint16_t* __restrict__ codes, int64_t ld, int r0, int cb, WalkState& S,
                           uint16_t* __restrict__ win, int lane, uint32_t* __restrict__ cig, int64_t cap) {
   if (S.done) return;
   // Every lane holds the same walk state; saying so lets the compiler keep it in scalar registers
@@ -69,7 +72,7 @@ __device__ void walk_core(const uint16_t* __restrict__ codes, int64_t ld, int r0
     g0 = (ii - r0 - 1) / kWfR;
     c0 = jj;
     ilo = r0 + max(1, (g0 - kWalkGroups + 1) * kWfR + 1);
-    jlo = max(1, c0 - kWalkCols + 1);
+    jlo = max(cb + 1, c0 - kWalkCols + 1);
     // Every load of the window is issued before the first LDS write, so the reload costs one memory
     // latency rather than one per code.  A window cell outside the segment (row group < 0 or column
     // < 1) loads the in-bounds cell (g0, c0) instead; it lies before row ilo or column jlo, so code()
@@ -119,6 +122,7 @@ __device__ void walk_core(const uint16_t* __restrict__ codes, int64_t ld, int r0
         break;
       }
       if (i == r0) break;  // the segment above holds this cell
+      if (cb > 0 && j == cb) break;  // the columns left of cb hold it
       if (i < ilo || j < jlo) load(i, j);
       // lanes t <= lim look at cells inside the window; the others read (i, j) and count as a
       // non-diagonal code, which ends the run
@@ -154,6 +158,7 @@ __device__ void walk_core(const uint16_t* __restrict__ codes, int64_t ld, int r0
       }
     } else {
       if (state == 1 && i == r0) break;  // the vertical gap goes on in the segment above
+      if (cb > 0 && j == cb) break;       // the gap goes on in (or ends at) a column left of cb
       // A gap run, up to 64 steps at a time: lane t looks at the t-th cell of the run.  The run goes
       // on through a cell whose extension bit is set and which is not in row (column) 1; the first
       // cell that ends it is stepped through and returns the walk to H, unless it lies outside the

@@ -1283,7 +1283,7 @@ __global__ __launch_bounds__(256) void wf_finish_kernel(const KParams P, WfWs W,
       }
       WalkState S;
       walk_start(S, r.q_end, r.s_end);
-      walk_core<MODE>(W.codes + pr.code_off, m, 0, S, walk_win[threadIdx.x >> 6], lane, cg, cap);
+      walk_core<MODE>(W.codes + pr.code_off, m, 0, 0, S, walk_win[threadIdx.x >> 6], lane, cg, cap);
       const int64_t runs = walk_finish(S, lane, cg, cap);
       r.q_begin = S.i;
       r.s_begin = S.j;

@@ -75,6 +75,33 @@ def test_linear_space_shapes(gpu, small_budget, mode, gap):
 
 
 @pytest.mark.parametrize("mode", [0, 1, 2], ids=["global", "local", "semi"])
+@pytest.mark.parametrize("gap", [(0, -1), (-3, -1)], ids=["linear", "affine"])
+def test_linear_space_window_fallback(gpu, small_budget, mode, gap):
+    """A path that leaves its segment's window on the left: the subject is the 8192-letter query with 7,000
+    unrelated letters inserted after its first 4096, so the alignment deletes them (with affine gaps in one
+    horizontal gap on row 4096; the two halves score 2 x 12,288, more than the gap costs, in every mode).  The segment of
+    rows 3073..4096 is relaxed again first only in a window of about 5,000 columns left of the walk; the
+    walk stops at the window's edge inside the gap, the tiles left of it are relaxed again and the walk
+    goes on.  Equal to the oracle's canonical traceback; and with 100 inserted letters, which stay in the
+    window, too."""
+    rng = np.random.default_rng(95 + mode)
+    go, ge = gap
+    sc = oracle.Scoring.simple(mode, 4, 3, -3, go, ge)
+    for ins in (7000, 100):
+        q = rng.integers(0, 4, 8192, dtype=np.uint8)
+        s = np.concatenate([q[:4096], rng.integers(0, 4, ins, dtype=np.uint8), q[4096:]])
+        print("mode %d gap %s insertion %d" % (mode, gap, ins), flush=True)
+        got = _run_ls(q, s, mode, 4, go, ge, match=3, mismatch=-3)
+        r = oracle.align(sc, q, s, traceback=True, impl="checkpointed")
+        exp = (r.score, r.q_begin, r.q_end, r.s_begin, r.s_end, r.cigar, 0)
+        assert got == exp, (ins, got[:5], exp[:5])
+        if ins == 7000 and go < 0:
+            # affine gaps: one deletion run carries the walk past the window's edge (linear gaps may spread
+            # the deletions over many rows)
+            assert max(L for L, op in exp[5] if op == 2) >= 6000, exp[5][:8]
+
+
+@pytest.mark.parametrize("mode", [0, 1, 2], ids=["global", "local", "semi"])
 def test_linear_space_gaps_across_boundaries(gpu, small_budget, mode):
     """Long gaps that cross a segment boundary (row 1024) and a tile column boundary (column 2048)."""
     rng = np.random.default_rng(90 + mode)
