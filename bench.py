@@ -14,7 +14,8 @@ Workloads (synth/__init__.py has the recipes):
            request stream below at 20,000 requests/s with p50/p99 latency per class.
   reads    1,048,576 read/window pairs, semi-global affine (-5/-2, +1/-4), CIGAR for every pair
   long     1 pair 262144 x 262144 DNA, local affine (-3/-1, +2/-3), score + end cell
-  long_tb  the same pair with its CIGAR
+  long_tb  the same pair with its CIGAR, a 4-bit code stored per cell (34 GB; --linear-space: the library's
+           default for pairs above 2^24 cells, checkpoints and tiles relaxed again)
   long_tb_393216  a 393216 x 393216 pair made the same way, with its CIGAR: its 4-bit codes would take 72 GiB,
            so the traceback runs in linear space
   nw1k     1 pair 1000 x 1000 DNA, global linear (+2/-1, gap -1), CIGAR
@@ -405,8 +406,8 @@ def main():
                     help="batch workloads: skip the graph / per-length-bin / one-pair-per-call comparisons")
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--linear-space", action="store_true",
-                    help="long_tb: trace back in linear space (checkpoints, tiles relaxed again) even where the "
-                         "4-bit codes of every cell would fit")
+                    help="long_tb: trace back in linear space (checkpoints, tiles relaxed again), the library's "
+                         "default above 2^24 cells, instead of storing the 4-bit code of every cell")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the library has no multi-GPU path", file=sys.stderr)
@@ -447,6 +448,8 @@ def main():
         if long_path:
             if args.linear_space:
                 flags |= aln.LINEAR_SPACE
+            elif flags & aln.TRACEBACK:
+                flags |= aln.STORED_CODES  # a code per cell (while it fits), as the workload's name says
             ba = aln.LongAligner(aln.scoring_of(w), q[:int(n[0])], s[:int(m[0])], flags)
         else:
             ba = aln.BatchAligner(aln.scoring_of(w), q, qo, s, so, int(n.max()), int(m.max()), flags)
@@ -521,7 +524,8 @@ def main():
         "dtype": dtype, "data": "synthetic (seeded generator, synth/__init__.py)",
         "config": {"workload": w.name, "pairs": w.n_pairs, "cells": cells, "mode": MODE_NAME[w.mode], "gap": gap,
                    "gap_open": w.gap_open, "gap_extend": w.gap_extend, "traceback": bool(w.traceback),
-                   "linear_space": bool(flags & aln.LINEAR_SPACE)},
+                   "linear_space": bool(flags & aln.LINEAR_SPACE) or bool(
+                       flags & aln.TRACEBACK and w.n_pairs == 1 and (int(n[0]) + 256) // 2 * int(m[0]) > (64 << 30))},
         "parity": check,
         "roofline": roof,
     }

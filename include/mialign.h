@@ -92,7 +92,9 @@ typedef struct {
 #define ALN_FORCE_INT16 4u /* accepted, no effect: local pairs run in 16 bits under the saturation check
                               (best < 32767) whatever the a-priori bound; kept for existing callers */
 #define ALN_LINEAR_SPACE 8u /* aln_align_long with ALN_TRACEBACK: trace back in linear space (checkpoints and
-                               tiles relaxed again) even where a code per cell would fit */
+                               tiles relaxed again) also for pairs of at most 2^24 cells */
+#define ALN_STORED_CODES 16u /* aln_align_long with ALN_TRACEBACK: store a code per cell also above 2^24 cells
+                               (while the codes take at most 64 GiB); ignored with ALN_LINEAR_SPACE */
 
 /* result flags */
 #define ALN_RES_INT32_REDO 1u  /* the 16-bit pass saturated; the pair was recomputed in 32 bits */
@@ -271,16 +273,18 @@ aln_status_t aln_long_workspace_size(const aln_scoring_t* scoring, int64_t n, in
  * each publishing its last row to the next), all bands drawn from one device-side work queue.
  *   q             DEVICE  n uint8 codes;  s  DEVICE  m uint8 codes
  *   flags         ALN_SCORE_ONLY, or ALN_TRACEBACK to also write the canonical CIGAR, optionally
- *                 | ALN_LINEAR_SPACE
+ *                 | ALN_LINEAR_SPACE or | ALN_STORED_CODES
  *   out           DEVICE  one aln_result_t (q_begin = s_begin = -1 when score-only)
  *   cigar         DEVICE  CIGAR words, cigar_capacity of them (n + m always suffice); NULL when
  *                         score-only.  A short buffer gives ALN_RES_CIGAR_TRUNC and the required count.
  *   workspace     DEVICE  at least aln_long_workspace_size(...) bytes, 256-byte aligned: two bottom-row
  *                         slots of (m + 1) * 8 bytes, plus, with ALN_TRACEBACK, either the 4-bit
- *                         predecessor code of every cell (about n * m / 2 bytes, while that is at most
- *                         64 GiB and ALN_LINEAR_SPACE is not given), or the linear-space traceback's
- *                         checkpoints (the H and E of every 1024th row and the H and F of every 2048th
- *                         column, about n * m / 85 bytes) and one segment of codes (aln_set_traceback_budget).
+ *                         predecessor code of every cell (about n * m / 2 bytes: pairs of at most 2^24
+ *                         cells, or with ALN_STORED_CODES while that is at most 64 GiB), or the
+ *                         linear-space traceback's checkpoints (the H and E of every 1024th row and the H
+ *                         and F of every 2048th column, about n * m / 85 bytes) and one segment of codes
+ *                         (aln_set_traceback_budget).  Above 2^24 cells the linear-space traceback is
+ *                         also the faster one on MI355X (it writes no code for most cells).
  * Traceback in linear space (Sec. III-A): the forward pass keeps the checkpoints; the walk then goes back
  * through segments of rows, bottom first, relaxing each segment's tiles again from the checkpoints (the
  * same integers as the forward pass) and walking its codes.  At most twice the cells are relaxed.
@@ -296,8 +300,8 @@ aln_status_t aln_align_long(const aln_scoring_t* scoring, const uint8_t* q, int6
  * both.  Returns ALN_E_INVALID for a negative size. */
 aln_status_t aln_set_batch_code_arena(int64_t bytes);
 
-/* Bytes of 4-bit predecessor codes a linear-space traceback (aln_align_long with ALN_LINEAR_SPACE, or
- * above 64 GiB of codes) holds at once: the rows of a segment that the traceback relaxes again in one go
+/* Bytes of 4-bit predecessor codes a linear-space traceback (aln_align_long with ALN_TRACEBACK above 2^24
+ * cells, or with ALN_LINEAR_SPACE) holds at once: the rows of a segment that the traceback relaxes again in one go
  * are as many as fit (at least 1024).  A smaller budget means more segments, each relaxed and walked in
  * turn.  0 restores the default of 4 GiB.  Process-wide; read when a size query or align call is made,
  * so the same value must hold for both.  Returns ALN_E_INVALID for a negative size. */

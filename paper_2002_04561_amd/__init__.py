@@ -19,7 +19,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmialign.so")
 
 GLOBAL, LOCAL, SEMIGLOBAL = 0, 1, 2
-SCORE_ONLY, TRACEBACK, FORCE_INT32, FORCE_INT16, LINEAR_SPACE = 0, 1, 2, 4, 8
+SCORE_ONLY, TRACEBACK, FORCE_INT32, FORCE_INT16, LINEAR_SPACE, STORED_CODES = 0, 1, 2, 4, 8, 16
 RES_INT32_REDO, RES_CIGAR_TRUNC, RES_BAD_CODE, RES_TOO_LONG, RES_DEVICE_ERROR, RES_BAD_END = 1, 2, 4, 8, 16, 32
 CIGAR_M, CIGAR_I, CIGAR_D = 0, 1, 2
 

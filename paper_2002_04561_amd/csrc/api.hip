@@ -388,16 +388,23 @@ aln_status_t aln_cigar_to_gapped(const uint8_t* q, int64_t n, const uint8_t* s, 
   return ALN_OK;
 }
 
-// Traceback of one long pair stores 4 bits per cell while that fits under this; above it (or with
-// ALN_LINEAR_SPACE) the pair is traced back in linear space from checkpoints.
+// Traceback of one long pair stores 4 bits per cell for pairs of at most kLsAutoCells cells (or with
+// ALN_STORED_CODES) while that fits under kMaxLongCodeBytes; otherwise (or with ALN_LINEAR_SPACE) the
+// pair is traced back in linear space from checkpoints.
 static const int64_t kMaxLongCodeBytes = (int64_t)64 << 30;
+
+static const int64_t kLsAutoCells = (int64_t)1 << 24;
 
 static bool long_linear_space(int64_t n, int64_t m, uint32_t flags) {
   if (!(flags & ALN_TRACEBACK)) return false;
-  return (flags & ALN_LINEAR_SPACE) || (n + kWfBand) / 2 * m > kMaxLongCodeBytes;
+  if (flags & ALN_LINEAR_SPACE) return true;
+  // codes that would not fit; and above 2^24 cells the linear-space traceback is faster (the forward
+  // pass writes no code per cell, and the tiles relax only a window around the path)
+  return (n + kWfBand) / 2 * m > kMaxLongCodeBytes || (!(flags & ALN_STORED_CODES) && n * m > kLsAutoCells);
 }
 
-static const uint32_t kLongFlags = ALN_TRACEBACK | ALN_FORCE_INT32 | ALN_FORCE_INT16 | ALN_LINEAR_SPACE;
+static const uint32_t kLongFlags =
+    ALN_TRACEBACK | ALN_FORCE_INT32 | ALN_FORCE_INT16 | ALN_LINEAR_SPACE | ALN_STORED_CODES;
 
 // Bytes of predecessor codes a linear-space traceback holds at once (aln_set_traceback_budget).
 static int64_t g_ls_budget = kLsCodeBudget;

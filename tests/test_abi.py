@@ -85,7 +85,7 @@ def test_long_size_query_host_checks():
     """aln_long_workspace_size refuses, before any device query, an unknown flag, a score range beyond exact
     32-bit lanes (ALN_E_SCORING), an invalid mode and a negative length (ALN_E_INVALID).  A traceback
     above 64 GiB of codes is no longer refused: it runs in linear space."""
-    cases = [(aln.Scoring(1, 4, -3, -1, 2, -3), 400000, 400000, aln.TRACEBACK | 16, -1),
+    cases = [(aln.Scoring(1, 4, -3, -1, 2, -3), 400000, 400000, aln.TRACEBACK | 32, -1),
              (aln.Scoring(1, 4, -3, -1, 100, -3), 3000000, 3000000, 0, -3),
              (aln.Scoring(5, 4, -3, -1, 2, -3), 10, 10, 0, -1),
              (aln.Scoring(1, 4, -3, -1, 2, -3), -1, 10, 0, -1)]

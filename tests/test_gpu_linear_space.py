@@ -1,5 +1,5 @@
-"""Linear-space traceback of one pair (aln_align_long with ALN_LINEAR_SPACE, and every traceback above 64 GiB
-of codes): checkpoint rows and columns kept by the forward pass, tiles relaxed again segment by segment,
+"""Linear-space traceback of one pair (aln_align_long with ALN_LINEAR_SPACE, every traceback above 2^24 cells
+unless ALN_STORED_CODES asks for a code per cell, and every one above 64 GiB of codes): checkpoint rows and columns kept by the forward pass, tiles relaxed again segment by segment,
 bottom first, and walked.  The canonical CIGAR, begin and end cells must equal the oracle's (full
 matrices, Sec. III-A) on every shape; a small code budget forces segments of 1024 rows, so walks cross
 many segment and tile boundaries, inside gaps too.  At full size the linear-space CIGAR of the 262144^2
@@ -35,7 +35,8 @@ def _run_ls(q, s, mode, A, go, ge, match=None, mismatch=None, subst=None, linear
     sc = aln.Scoring(mode, A, go, ge, match=match or 0, mismatch=mismatch or 0, subst=subst)
     qd = torch.from_numpy(np.ascontiguousarray(q, dtype=np.uint8) if len(q) else np.zeros(1, np.uint8)).cuda()
     sd = torch.from_numpy(np.ascontiguousarray(s, dtype=np.uint8) if len(s) else np.zeros(1, np.uint8)).cuda()
-    flags = aln.TRACEBACK | (aln.LINEAR_SPACE if linear else 0)
+    # linear=False asks for a code per cell (ALN_STORED_CODES), which the library still refuses above 64 GiB
+    flags = aln.TRACEBACK | (aln.LINEAR_SPACE if linear else aln.STORED_CODES)
     la = aln.LongAligner(sc, qd[:len(q)], sd[:len(s)], flags=flags)
     la.run()
     torch.cuda.synchronize()

@@ -105,7 +105,8 @@ def _run_tb(q, s, mode, A, go, ge, match=None, mismatch=None, subst=None, cap=No
     sc = aln.Scoring(mode, A, go, ge, match=match or 0, mismatch=mismatch or 0, subst=subst)
     qd = torch.from_numpy(np.ascontiguousarray(q, dtype=np.uint8) if len(q) else np.zeros(1, np.uint8)).cuda()
     sd = torch.from_numpy(np.ascontiguousarray(s, dtype=np.uint8) if len(s) else np.zeros(1, np.uint8)).cuda()
-    la = aln.LongAligner(sc, qd[:len(q)], sd[:len(s)], flags=aln.TRACEBACK, cigar_capacity=cap)
+    # a code per cell at every size (the linear-space traceback has tests of its own)
+    la = aln.LongAligner(sc, qd[:len(q)], sd[:len(s)], flags=aln.TRACEBACK | aln.STORED_CODES, cigar_capacity=cap)
     la.run()
     torch.cuda.synchronize()
     r = la.result()
