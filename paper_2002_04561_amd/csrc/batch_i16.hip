@@ -92,9 +92,11 @@ __host__ __device__ constexpr int i16_chunk_words(int R) { return R / 2 < 4 ? R 
 __host__ __device__ constexpr int i16_wave_prof_words(int AP, int R) { return AP * 128 * (R / 2) + 64; }
 static_assert(kI16ProfBase % 256 == 0, "profiles start on a bank sweep");
 
-__device__ __forceinline__ bool fits16(const KParams& P, int n, int m) {
+// biased: values carry the row bias of the global and semi-global recurrence (Hb = H - i*ge), which
+// lifts them by at most n*|ge|
+__device__ __forceinline__ bool fits16(const KParams& P, int n, int m, bool biased) {
   const int mn = n < m ? n : m;
-  const long long up = (long long)mn * (P.sigma_max > 0 ? P.sigma_max : 0);
+  const long long up = (long long)mn * (P.sigma_max > 0 ? P.sigma_max : 0) - (biased ? (long long)n * P.ge : 0);
   const long long lo = 3ll * P.go + (long long)(n + m) * P.ge;
   return up <= kBound16 && lo >= -kBound16 && m < 32767;
 }
@@ -116,6 +118,12 @@ __global__ __launch_bounds__(kI16Block) void batch_i16_kernel(
     size_t letters_off, size_t dirs_off, const int* __restrict__ idx, const int* __restrict__ idx_count,
     int* __restrict__ redo_idx, int* __restrict__ redo_cnt, int* __restrict__ ticket) {
   static_assert(R % 8 == 0 || R == 4, "R must be 4 or a multiple of 8");
+  // Global and semi-global pairs keep their values with a row bias, Hb(i, j) = H(i, j) - i*ge (and so
+  // E and F): then Eb(i, j) = max(Eb(i-1, j), Hb(i-1, j) + go) extends a vertical gap with no add,
+  // Hb(i, j) = max(Hb(i-1, j-1) + sigma - ge, Eb, Fb), and Fb is unchanged -- Eqs. (1), (4), (5) with
+  // every term of row i shifted by the same constant.  Local pairs, whose floor H = 0 would become a
+  // per-row constant, keep plain values.
+  constexpr bool kBias = MODE != ALN_LOCAL;
   extern __shared__ char smem[];
   int32_t* tab = reinterpret_cast<int32_t*>(smem);
   for (int k = threadIdx.x; k < kTab * kTab; k += blockDim.x) {
@@ -124,7 +132,8 @@ __global__ __launch_bounds__(kI16Block) void batch_i16_kernel(
     if (a >= P.alphabet || b >= P.alphabet)
       v = kPadSigma16;
     else
-      v = P.use_table ? (int32_t)P.sig[a * kMaxAlphabet + b] : (a == b ? P.match : P.mismatch);
+      v = (P.use_table ? (int32_t)P.sig[a * kMaxAlphabet + b] : (a == b ? P.match : P.mismatch)) -
+          (kBias ? P.ge : 0);
     tab[k] = v;
   }
   __syncthreads();
@@ -184,7 +193,7 @@ __global__ __launch_bounds__(kI16Block) void batch_i16_kernel(
         } else {
           nn[h] = (int)a;
           mm[h] = (int)b;
-          const bool f = fits16(P, nn[h], mm[h]);
+          const bool f = fits16(P, nn[h], mm[h], kBias);
           ok16[h] = f || (MODE == ALN_LOCAL && mm[h] < 32767);
         }
       }
@@ -267,13 +276,14 @@ __global__ __launch_bounds__(kI16Block) void batch_i16_kernel(
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         const int i = i0 + 1 + r;
-        hl[r] = sp((MODE == ALN_GLOBAL) ? P.go + i * P.ge : 0);
+        hl[r] = sp((MODE == ALN_GLOBAL) ? P.go + (kBias ? 0 : i * P.ge) : (kBias ? -i * P.ge : 0));
         f[r] = neg2;
         bv[r] = sp(-32768);
         bjr[r] = zero;
         cap[r] = zero;
       }
-      s2 hdiag = sp((MODE == ALN_GLOBAL && i0 > 0) ? P.go + i0 * P.ge : 0);
+      // H(i0, 0), with the row bias where it applies
+      s2 hdiag = sp((MODE == ALN_GLOBAL && i0 > 0) ? P.go + (kBias ? 0 : i0 * P.ge) : (kBias ? -i0 * P.ge : 0));
       const int rnA = nn[0] - 1 - i0, rnB = nn[1] - 1 - i0;
       const bool lastA = rnA >= 0 && rnA < R, lastB = rnB >= 0 && rnB < R;
       const bool track_last = (MODE == ALN_SEMIGLOBAL) && __any(lastA || lastB);
@@ -326,8 +336,8 @@ __global__ __launch_bounds__(kI16Block) void batch_i16_kernel(
           const s2 sg = from_bits(__builtin_amdgcn_perm(wb[r / 2], wa[r / 2], (r & 1) ? 0x07060302u : 0x05040100u));
           const s2 hlo = hl[r];
           const s2 d = adds(hd, sg);
-          const s2 tup = adds(hup, goe2);
-          const s2 e = AFFINE ? mx(adds(eup, ge2), tup) : adds(hup, ge2);
+          const s2 tup = adds(hup, kBias ? go2 : goe2);
+          const s2 e = AFFINE ? mx(kBias ? eup : adds(eup, ge2), tup) : (kBias ? hup : adds(hup, ge2));
           const s2 tle = adds(hlo, goe2);
           const s2 ff = AFFINE ? mx(adds(f[r], ge2), tle) : adds(hlo, ge2);
           s2 hv = mx(mx(d, e), ff);
@@ -375,7 +385,7 @@ __global__ __launch_bounds__(kI16Block) void batch_i16_kernel(
 #pragma unroll
           for (int r = 0; r < R; ++r) hw[r] = bits(hl[r]);
           const s2 hn = from_bits(tree_pick<R>(hw, rnb));
-          const int va = lo16(hn), vb = hi16(hn);
+          const int va = lo16(hn) + (kBias ? nn[0] * P.ge : 0), vb = hi16(hn) + (kBias ? nn[1] * P.ge : 0);
           if (lastA && j <= mm[0] && va > brow[0]) {
             brow[0] = va;
             browj[0] = j;
@@ -432,7 +442,7 @@ __global__ __launch_bounds__(kI16Block) void batch_i16_kernel(
               bj[h] = h ? hi16(bjr[r]) : lo16(bjr[r]);
             }
           } else {
-            const int v = h ? hi16(cap[r]) : lo16(cap[r]);
+            const int v = (h ? hi16(cap[r]) : lo16(cap[r])) + (kBias ? i * P.ge : 0);
             if (MODE == ALN_SEMIGLOBAL && i < nn[h] && v > best[h]) {
               best[h] = v;
               bi[h] = i;
