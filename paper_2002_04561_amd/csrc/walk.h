@@ -22,9 +22,9 @@ __device__ void walk_back(CodeFn code, int i, int j, uint32_t* cig, int64_t cap,
   int state = 0;  // 0 = H, 1 = E, 2 = F
   int64_t runs = 0;
   uint32_t cur_op = 0xffu, cur_len = 0;
-  auto push = [&](uint32_t op) {
+  auto push_n = [&](uint32_t op, uint32_t len) {
     if (op == cur_op) {
-      ++cur_len;
+      cur_len += len;
       return;
     }
     if (cur_len) {
@@ -32,32 +32,42 @@ __device__ void walk_back(CodeFn code, int i, int j, uint32_t* cig, int64_t cap,
       ++runs;
     }
     cur_op = op;
-    cur_len = 1;
+    cur_len = len;
   };
+  auto push = [&](uint32_t op) { push_n(op, 1); };
   for (;;) {
     if (state == 0) {
       if (i == 0 || j == 0) {
         if (MODE == ALN_GLOBAL) {
-          while (j > 0) {
-            push(ALN_CIGAR_D);
-            --j;
-          }
-          while (i > 0) {
-            push(ALN_CIGAR_I);
-            --i;
-          }
+          if (j > 0) push_n(ALN_CIGAR_D, (uint32_t)j);
+          if (i > 0) push_n(ALN_CIGAR_I, (uint32_t)i);
+          i = 0;
+          j = 0;
         }
         break;
       }
-      const uint32_t hs = code(i, j) & 3u;
-      if (hs == 3u) break;
-      if (hs == 0u) {
-        push(ALN_CIGAR_M);
-        --i;
-        --j;
-      } else {
-        state = (int)hs;
-      }
+      // The next kDiag cells along the diagonal are read together, so their loads are in flight at
+      // once; the walk takes the diagonal moves among them up to the first cell that is not one (or
+      // the matrix border), which it then handles from the code already read.
+      constexpr int kDiag = 8;
+      const int lim = min(min(i, j), kDiag);
+      uint32_t hs[kDiag];
+#pragma unroll
+      for (int t = 0; t < kDiag; ++t) hs[t] = t < lim ? (code(i - t, j - t) & 3u) : 0u;
+      int k = 0;
+      uint32_t stop = 0u;
+#pragma unroll
+      for (int t = kDiag - 1; t >= 0; --t)
+        if (t < lim && hs[t] != 0u) {
+          k = t;
+          stop = hs[t];
+        }
+      if (stop == 0u) k = lim;  // every cell read is a diagonal move
+      if (k > 0) push_n(ALN_CIGAR_M, (uint32_t)k);
+      i -= k;
+      j -= k;
+      if (stop == 3u) break;
+      if (stop != 0u) state = (int)stop;
     } else if (state == 1) {
       const uint32_t c = code(i, j);
       push(ALN_CIGAR_I);
