@@ -228,12 +228,20 @@ def _sub_aligner(w, idx, flags, config=None):
                             config=config), sub
 
 
-def time_per_bin(w, flags, stream, steps, config=None):
-    """One aln_align_batch call per length bin (bins of log2 max(n, m)), run back to back on one stream."""
+def time_per_bin(w, flags, stream, steps, config=None, tune_each=False):
+    """One aln_align_batch call per length bin (bins of log2 max(n, m)), run back to back on one stream: with
+    the given config, or (tune_each) with each bin's own config from the autotuner.  Returns (ms per pass,
+    number of calls, the bins' configs)."""
     import torch
     n, m = w.lengths()
     key = np.log2(np.maximum(np.maximum(n, m), 1)).astype(int)
     calls = [_sub_aligner(w, np.nonzero(key == b)[0], flags, config)[0] for b in np.unique(key)]
+    cfgs = []
+    if tune_each:
+        from paper_2002_04561_amd import tune
+        for ba in calls:
+            cfg, _ = tune.tune(ba, stream)
+            cfgs.append(dict(cfg.__dict__))
     for ba in calls:
         ba.run(stream)
     torch.cuda.synchronize()
@@ -242,7 +250,7 @@ def time_per_bin(w, flags, stream, steps, config=None):
         for ba in calls:
             ba.run(stream)
     torch.cuda.synchronize()
-    return (time.perf_counter() - t0) * 1e3 / steps, len(calls)
+    return (time.perf_counter() - t0) * 1e3 / steps, len(calls), cfgs
 
 
 def time_plain(w, flags, stream, count, seed=1):
@@ -536,10 +544,16 @@ def main():
         out["graph"] = {"ms_per_step": round(gms, 4), "gcups": round(cells / (gms * 1e-3) / 1e9, 2),
                         "what": "the same call captured once in a HIP graph, replayed"}
         log("graph replay: %.3f ms" % gms)
-        bms, nbins = time_per_bin(w, flags, stream, max(1, min(args.steps, 3)), ba.config)
+        bms, nbins, _ = time_per_bin(w, flags, stream, max(1, min(args.steps, 3)), ba.config)
         out["per_length_bin"] = {"ms_per_step": round(bms, 4), "gcups": round(cells / (bms * 1e-3) / 1e9, 2),
                                  "calls": nbins, "what": "one call per bin of log2 max(n, m), back to back"}
         log("per length bin: %.3f ms in %d calls" % (bms, nbins))
+        if not args.no_tune and not args.config:
+            tms, nbins, bcfgs = time_per_bin(w, flags, stream, max(1, min(args.steps, 3)), None, tune_each=True)
+            out["per_length_bin_tuned"] = {
+                "ms_per_step": round(tms, 4), "gcups": round(cells / (tms * 1e-3) / 1e9, 2), "calls": nbins,
+                "configs": bcfgs, "what": "one call per bin, each bin with its own autotuned config"}
+            log("per length bin, tuned per bin: %.3f ms" % tms)
         plain, pidx, pres = time_plain(w, flags, stream, args.plain_pairs)
         plain["parity"] = check_plain(pres, pidx, res)
         out["plain"] = plain
