@@ -100,6 +100,7 @@ struct WfWs {
   int2* ckcols;      // checkpointed forward pass (one pair), else null: [k][row - 1] Hb and Fb of column
                      // (k + 1) * kTileCols; its row slots hold every group's bottom row
   int64_t ck_ld;     // rows of a checkpoint column (a multiple of the band height)
+  int one_pair;      // aln_align_long: one pair, its bands spread over the whole device
 };
 
 struct WfOffsets {

@@ -75,6 +75,13 @@ __device__ __forceinline__ void raise_local_floors(int32_t (&bv)[R], const int32
   for (int r = 0; r < R; ++r) bv[r] = max(bv[r], fl + nu[r]);
 }
 
+// Per lane, a where the lane's bit of mask is set, else b: one v_cndmask, never a branch.
+__device__ __forceinline__ int mask_select(unsigned long long mask, int a, int b) {
+  int r;
+  asm("v_cndmask_b32_e64 %0, %1, %2, %3" : "=v"(r) : "v"(b), "v"(a), "s"(mask));
+  return r;
+}
+
 // c ? a : b as one v_cndmask on the lane mask of c, so the compiler cannot turn the choice into a
 // branch around the computation of a
 __device__ __forceinline__ int lane_select(bool c, int a, int b) {
@@ -436,7 +443,7 @@ __global__ __launch_bounds__(kWfBlockAlone) void wf_i32_kernel(const KParams P, 
 // CKPT: also store checkpoints for a linear-space traceback (one pair, groups aligned with its bands):
 // every group's bottom row stays in its own row slot instead of two rotating ones, and every
 // kTileCols-th column's H and F of all rows go to W.ckcols.
-template <int MODE, bool AFFINE, int PROF, bool TB, int R, bool P16, bool CKPT>
+template <int MODE, bool AFFINE, int PROF, bool TB, int R, bool P16, bool CKPT, bool LAZY>
 __global__ __launch_bounds__(kWfBlock) void wf_i32_group_kernel(const KParams P, const uint8_t* __restrict__ Q,
                                                           const uint8_t* __restrict__ S, WfWs W) {
   static_assert(PROF != kProfLane || R == 4, "a lane profile word holds 4 rows");
@@ -454,6 +461,7 @@ __global__ __launch_bounds__(kWfBlock) void wf_i32_group_kernel(const KParams P,
   static_assert(!P16 || (MODE == ALN_LOCAL && (PROF == kProfReg || PROF == kProfLane) && !TB && R == 4),
                 "packed bands: local, score only, register or per-lane profiles");
   static_assert(!CKPT || (!TB && !P16 && R == 4), "checkpoints: 32-bit score-only bands");
+  static_assert(!LAZY || (MODE == ALN_LOCAL && !TB && !P16 && !CKPT), "kept groups: local 32-bit score-only bands");
   // packed bands: the upper half's bottom row (absolute H, E) on its way to the lower half
   __shared__ int2 dline[P16 ? kWfWavesPerBlock : 1][P16 ? kDelayRing : 1];
   for (int k = threadIdx.x; k < kTab * kTab; k += blockDim.x) {
@@ -1007,6 +1015,34 @@ __global__ __launch_bounds__(kWfBlock) void wf_i32_group_kernel(const KParams P,
     };
     int c_next = lane < BLK ? letter_raw(1 + lane) : -1;
 
+    // LAZY (local, score-only): a row that beats its best in a group of 4 steps keeps that group (its
+    // first step sg and its 4 H values sv) instead of finding the first maximal step at once; resolve()
+    // turns the kept group into the row's column before any cell-by-cell update and after the band's
+    // last step.  The result is the same (a later strict improvement replaces the kept group, as it
+    // would replace the column), and the improving groups -- hundreds per band where the bands meet
+    // the alignment's diagonal -- cost 20 selects instead of a search.  Every step a band spends there
+    // also delays each band below it, which is what the selects save.
+    int32_t sv[4][R];
+    int sg[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      sg[r] = -1;
+      sv[0][r] = sv[1][r] = sv[2][r] = sv[3][r] = 0;
+    }
+    auto resolve = [&]() {
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        if (sg[r] >= 0) {
+          const int32_t mx = max(max(sv[0][r], sv[1][r]), max(sv[2][r], sv[3][r]));
+          int k = sv[2][r] == mx ? 2 : 3;
+          k = sv[1][r] == mx ? 1 : k;
+          k = sv[0][r] == mx ? 0 : k;
+          bj[r] = sg[r] - lane + 1 + k;
+          sg[r] = -1;
+        }
+      }
+    };
+
     const int steps = m + 63;
     for (int tb = 0; tb < steps; tb += BLK) {
       // lane-0 inputs for steps tb..tb+BLK-1 (columns tb+1..tb+BLK), held by lanes < BLK
@@ -1102,7 +1138,17 @@ __global__ __launch_bounds__(kWfBlock) void wf_i32_group_kernel(const KParams P,
               mk[r] = max(max(hk[0][r], hk[1][r]), max(hk[2][r], hk[3][r]));
               imp |= mk[r] > bv[r];
             }
-            if (imp) {
+            if (LAZY && imp) {
+              // a row that beat its best keeps the group (resolved later, see resolve)
+#pragma unroll
+              for (int r = 0; r < R; ++r) {
+                const unsigned long long up = __builtin_amdgcn_ballot_w64(mk[r] > bv[r]);
+#pragma unroll
+                for (int x = 0; x < 4; ++x) sv[x][r] = mask_select(up, hk[x][r], sv[x][r]);
+                sg[r] = mask_select(up, t0, sg[r]);
+                bv[r] = max(bv[r], mk[r]);
+              }
+            } else if (imp) {
               // a row that beat its best takes the group's maximum at the first of the 4 steps that
               // reached it, as a cell-by-cell strict update would
 #pragma unroll
@@ -1116,6 +1162,7 @@ __global__ __launch_bounds__(kWfBlock) void wf_i32_group_kernel(const KParams P,
             }
           }
         } else {
+          if (LAZY) resolve();
           step(t0, vh.x, ve.x, vc.x, std::true_type(), nullptr, CKPT);
           step(t0 + 1, vh.y, ve.y, vc.y, std::true_type(), nullptr, CKPT);
           step(t0 + 2, vh.z, ve.z, vc.z, std::true_type(), nullptr, CKPT);
@@ -1140,6 +1187,7 @@ __global__ __launch_bounds__(kWfBlock) void wf_i32_group_kernel(const KParams P,
       }
     }
 
+    if (LAZY) resolve();
     // band optimum: (score, i, j) over this lane's rows, then across the wave
     int bs = kNeg32, bi = 0, bjj = 0;
 #pragma unroll
@@ -1354,19 +1402,24 @@ void launch_wf_t(const KParams& kp, const uint8_t* q, const uint8_t* s, const Wf
   if (kCanPack && grouped && p16 && p16_exact(kp)) {
     // packed bands keep two 16-bit rows of each half per letter and lane: twice the words
     ProfScope prof("wavefront_p16", stream);
-    hipLaunchKernelGGL((wf_i32_group_kernel<MODE, AFFINE, PROF, TB, kWfR, kCanPack, false>), dim3(blocks),
+    hipLaunchKernelGGL((wf_i32_group_kernel<MODE, AFFINE, PROF, TB, kWfR, kCanPack, false, false>), dim3(blocks),
                        dim3(kWfBlock), 2 * lds, stream, kp, q, s, W);
     return;
   }
   if (!TB && W.ckcols) {
     ProfScope prof("wavefront_i32_checkpoints", stream);
-    hipLaunchKernelGGL((wf_i32_group_kernel<MODE, AFFINE, PROF, false, kWfR, false, !TB>), dim3(blocks),
+    hipLaunchKernelGGL((wf_i32_group_kernel<MODE, AFFINE, PROF, false, kWfR, false, !TB, false>), dim3(blocks),
                        dim3(kWfBlock), lds, stream, kp, q, s, W);
     return;
   }
   ProfScope prof(TB ? "wavefront_i32_traceback" : "wavefront_i32", stream);
-  if (grouped)
-    hipLaunchKernelGGL((wf_i32_group_kernel<MODE, AFFINE, PROF, TB, kWfR, false, false>), dim3(blocks),
+  // one long pair, local and score-only: improving groups are kept and resolved later (LAZY)
+  constexpr bool kLazy = MODE == ALN_LOCAL && !TB;
+  if (grouped && kLazy && W.one_pair)
+    hipLaunchKernelGGL((wf_i32_group_kernel<MODE, AFFINE, PROF, TB, kWfR, false, false, kLazy>), dim3(blocks),
+                       dim3(kWfBlock), lds, stream, kp, q, s, W);
+  else if (grouped)
+    hipLaunchKernelGGL((wf_i32_group_kernel<MODE, AFFINE, PROF, TB, kWfR, false, false, false>), dim3(blocks),
                        dim3(kWfBlock), lds, stream, kp, q, s, W);
   else
     hipLaunchKernelGGL((wf_i32_kernel<MODE, AFFINE, PROF, TB, kWfR>), dim3(blocks), dim3(kWfBlockAlone), lds,
@@ -1453,6 +1506,7 @@ WfWs wf_view(void* base_, const WfOffsets& o) {
   W.codes = reinterpret_cast<uint16_t*>(base + o.codes);
   W.ckcols = nullptr;
   W.ck_ld = 0;
+  W.one_pair = 0;
   return W;
 }
 
@@ -1501,6 +1555,7 @@ aln_status_t launch_long(const KParams& kp, const LongPlan& pl, const uint8_t* q
                          int64_t m, aln_result_t* out, uint32_t* cigar, int64_t cigar_cap, void* ws,
                          hipStream_t stream) {
   WfWs W = wf_view(ws, pl.off);
+  W.one_pair = 1;
   hipLaunchKernelGGL(wf_single_pair_kernel, dim3(1), dim3(64), 0, stream, W, (int)n, (int)m, kWfBand);
   // one pair: its bands are few per SIMD, so the grouped engine (no device-memory stalls in the
   // compute waves) is the faster one

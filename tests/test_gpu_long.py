@@ -67,6 +67,29 @@ def test_long_protein_table(gpu, mode):
         assert got == exp, (n, m, got, exp)
 
 
+@pytest.mark.parametrize("gap", [(0, -4), (-5, -2)], ids=["linear", "affine"])
+def test_long_local_ties_mid_band(gpu, gap):
+    """Local optima that end inside a band's range-free steps, with ties: one window of the query (a segment
+    and 60 letters either side) planted twice in an unrelated subject gives end cells of equal score in one
+    row; the one with the smaller column must be reported (the tie rule), also where a band keeps a row's
+    improving groups of steps and resolves them later."""
+    rng = np.random.default_rng(4242)
+    go, ge = gap
+    F = 60
+    for (n, m, L) in [(1000, 1500, 60), (2600, 2100, 90), (777, 3000, 40), (1300, 1300, 200)]:
+        q = rng.integers(0, 4, n, dtype=np.uint8)
+        s = rng.integers(0, 4, m, dtype=np.uint8)
+        a = int(rng.integers(100 + F, n - L - 100 - F))
+        b1 = int(rng.integers(100 + F, m // 2 - L - F))
+        b2 = int(rng.integers(m // 2 + F, m - L - 100 - F))
+        s[b1 - F:b1 + L + F] = q[a - F:a + L + F]
+        s[b2 - F:b2 + L + F] = q[a - F:a + L + F]
+        got = _run(q, s, 1, 4, go, ge, match=1, mismatch=-3)
+        exp = _oracle(q, s, 1, 4, go, ge, match=1, mismatch=-3)
+        assert got == exp, (n, m, L, got, exp)
+        assert exp[2] < b2 - F, (n, m, exp)  # the first copy's end cell
+
+
 def test_long_empty_and_bad(gpu):
     assert _run(np.zeros(0, np.uint8), np.array([1, 2], np.uint8), 0, 4, -3, -1, 2, -3)[:3] == (-5, 0, 2)
     assert _run(np.array([1, 2], np.uint8), np.zeros(0, np.uint8), 1, 4, -3, -1, 2, -3)[:3] == (0, 0, 0)
