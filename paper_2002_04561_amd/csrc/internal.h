@@ -101,10 +101,14 @@ struct WfWs {
                      // (k + 1) * kTileCols; its row slots hold every group's bottom row
   int64_t ck_ld;     // rows of a checkpoint column (a multiple of the band height)
   int one_pair;      // aln_align_long: one pair, its bands spread over the whole device
+  int64_t* order;    // [n_items] per-band engine: the item handed out at each ticket (see wf_order_kernel)
+  int* lv;           // [2 * n_lv - 1] per-band engine: level counts, positions and cursors of that order
+  int n_lv;          // more than the largest band count of any pair
 };
 
 struct WfOffsets {
-  size_t pairs, rows, flags, item_pair, res, misc, codes;
+  size_t pairs, rows, flags, item_pair, res, misc, codes, order, lv;
+  int64_t n_lv;
 };
 
 struct LongPlan {
