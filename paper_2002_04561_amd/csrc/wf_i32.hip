@@ -1377,13 +1377,27 @@ __global__ void wf_reset_kernel(WfWs W) {
 __global__ __launch_bounds__(256) void wf_level_hist_kernel(WfWs W) {
   const int np = *W.n_pairs;
   const int L = W.n_lv - 1;
-  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < np; p += (int64_t)gridDim.x * blockDim.x) {
-    const int nb = W.pairs[p].nb;
-    if (nb > 0 && nb <= L) {
-      atomicAdd(&W.lv[nb], 1);
-      atomicMax(&W.lv[0], nb);
+  const int lane = threadIdx.x & 63;
+  int mx = 0;
+  for (int64_t p0 = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63); p0 < np;
+       p0 += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t p = p0 + lane;
+    const int nb = p < np ? W.pairs[p].nb : 0;
+    mx = max(mx, nb);
+    // one atomic per distinct band count among the wave's pairs (the planner's order keeps them few)
+    bool left = nb > 0 && nb <= L;
+    while (__builtin_amdgcn_ballot_w64(left) != 0) {
+      const unsigned long long lm = __builtin_amdgcn_ballot_w64(left);
+      const int first = (int)__builtin_ctzll(lm);
+      const int v = __shfl(nb, first, 64);
+      const bool same = left && nb == v;
+      const unsigned long long sm = __builtin_amdgcn_ballot_w64(same);
+      if (lane == first) atomicAdd(&W.lv[v], (int)__builtin_popcountll(sm));
+      left = left && !same;
     }
   }
+  mx = __ockl_wfred_max_i32(mx);
+  if (lane == 0 && mx > 0) atomicMax(&W.lv[0], min(mx, L));
 }
 
 // One block: level b holds the pairs with more than b bands; its items start after those of levels
@@ -1455,15 +1469,26 @@ __global__ __launch_bounds__(256) void wf_order_kernel(WfWs W) {
       nb = pr.nb <= L ? pr.nb : 0;
       it0 = pr.item0;
     }
-    for (int b = 0;; ++b) {
-      const bool has = b < nb;
-      const unsigned long long mask = __builtin_amdgcn_ballot_w64(has);
-      if (mask == 0) break;
-      int at = 0;
-      if (lane == 0) at = atomicAdd(&cur[b], __builtin_popcountll(mask));
-      at = __shfl(at, 0, 64);
-      const int rank = __builtin_popcountll(mask & ((1ull << lane) - 1ull));
-      if (has) W.order[(int64_t)W.lv[1 + b] + at + rank] = it0 + b;
+    const int wmax = __ockl_wfred_max_i32(nb);
+    // 64 levels at a time: lane u counts the wave's pairs at level b0 + u, reserves their places with one
+    // atomic (all lanes' atomics in one instruction) and reads the level's first position
+    for (int b0 = 0; b0 < wmax; b0 += 64) {
+      const int nl = min(64, wmax - b0);
+      int mycnt = 0;
+      for (int u = 0; u < nl; ++u) {
+        const int cnt = (int)__builtin_popcountll(__builtin_amdgcn_ballot_w64(b0 + u < nb));
+        if (lane == u) mycnt = cnt;
+      }
+      int mybase = 0;
+      if (lane < nl && mycnt > 0) mybase = W.lv[1 + b0 + lane] + atomicAdd(&cur[b0 + lane], mycnt);
+      for (int u = 0; u < nl; ++u) {
+        const int b = b0 + u;
+        const bool has = b < nb;
+        const unsigned long long mask = __builtin_amdgcn_ballot_w64(has);
+        const int at = __shfl(mybase, u, 64);
+        const int rank = (int)__builtin_popcountll(mask & ((1ull << lane) - 1ull));
+        if (has) W.order[(int64_t)at + rank] = it0 + b;
+      }
     }
   }
 }
