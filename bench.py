@@ -34,31 +34,19 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Integer VALU rates of MI355X (256 CUs x 4 SIMDs at 2.4 GHz): a wave64 instruction takes 4 cycles of
-# a SIMD (16 lanes a cycle: 39.32 T lane-ops/s) -- max, max3, bit-field extract, DPP moves and every
-# packed 16-bit instruction -- except the 32-bit add, which takes 2 (32 lanes a cycle: 78.64 T, the
-# rate of the published 157.3 TFLOP/s fp32 FMA).  A microbenchmark of independent chains at 8 waves per
-# SIMD gave 63 T for v_add_u32, 70 T for v_add_f32 and 38 T for v_max_i32, v_max3_i32, v_bfe_i32 and
-# v_pk_add_u16.  Packed 16-bit instructions do two lane-ops each (78.64 T).
-RATE_SLOW_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
-RATE_ADD32_TOPS = 2 * RATE_SLOW_TOPS
-PEAK_I16_TOPS = 2 * RATE_SLOW_TOPS
+# Integer VALU peak of MI355X (256 CUs x 4 SIMDs at 2.4 GHz), in 2-input ops: a SIMD retires at most 32 a
+# cycle -- a 32-bit add takes 2 cycles per wave64 instruction, a 3-input max (two ops) or a packed 16-bit
+# instruction (two lanes) takes 4, and a 2-input max, a bit-field extract or a DPP move takes 4 for one op
+# a lane.  A microbenchmark of independent chains at 8 waves per SIMD measured 63 T lane-ops/s for
+# v_add_u32 (70 T for v_add_f32), 38 T instructions for v_max_i32, v_max3_i32, v_bfe_i32 and v_pk_add_u16.
+# 256 x 4 x 32 x 2.4e9 = 78.64 T ops/s bounds every mix of adds and maxes, in 32 or in packed 16 bits.
+PEAK_I32_TOPS = 256 * 4 * 32 * 2.4e9 / 1e12
+PEAK_I16_TOPS = PEAK_I32_TOPS
 
-# Algorithmic integer ops per DP cell (each 2-input add/sub/max and the substitution lookup count 1),
-# as in Eqs. (1)-(5) with the row bias (E's extension needs no add), and of them the 32-bit adds:
-# linear: sigma, diagonal add, left+g (adds), max3 (2) = 5; affine: E's open add and max, F's two adds
-# and max, sigma, diagonal add, max3 (2) = 10; local adds the floor and the optimum's compare.
+# Algorithmic integer ops per DP cell (each 2-input add/sub/max and the substitution lookup count 1):
+# linear: sigma, diagonal add, up+g, left+g, max3 (2) = 5 ... as in Eqs. (1)-(5).
 OPS_PER_CELL = {("global", "linear"): 5, ("semiglobal", "linear"): 5, ("local", "linear"): 7,
                 ("global", "affine"): 10, ("semiglobal", "affine"): 10, ("local", "affine"): 12}
-ADDS_PER_CELL = {("global", "linear"): 2, ("semiglobal", "linear"): 2, ("local", "linear"): 2,
-                 ("global", "affine"): 4, ("semiglobal", "affine"): 4, ("local", "affine"): 4}
-
-
-def peak_i32_tops(key):
-    """The 32-bit lanes' peak in algorithmic ops/s for a recurrence: its adds at the add rate, the rest at
-    the slow rate (local affine: 12 / (4 / 78.64 + 8 / 39.32) = 47.2 T)."""
-    ops, adds = OPS_PER_CELL[key], ADDS_PER_CELL[key]
-    return ops / (adds / RATE_ADD32_TOPS + (ops - adds) / RATE_SLOW_TOPS)
 MODE_NAME = {0: "global", 1: "local", 2: "semiglobal"}
 
 
@@ -524,7 +512,7 @@ def main():
     opc = OPS_PER_CELL[(MODE_NAME[w.mode], gap)]
     dom = max(((k, v) for k, v in prof.items() if k != "plan"), key=lambda kv: kv[1][1]) if prof else None
     dtype = "int16" if (dom and ("i16" in dom[0] or "p16" in dom[0])) else "int32"
-    peak = peak_i32_tops((MODE_NAME[w.mode], gap)) if dtype == "int32" else PEAK_I16_TOPS
+    peak = PEAK_I32_TOPS if dtype == "int32" else PEAK_I16_TOPS
     roof = None
     if dom:
         per_launch_ms = dom[1][1] / max(dom[1][0], 1)

@@ -312,8 +312,10 @@ __global__ __launch_bounds__(kWfBlockAlone) void wf_i32_kernel(const KParams P, 
           int32_t hn = 0;
           uint32_t word = 0;
           const int pw = PROF == kProfLane ? (int)lp[in_c] : 0;
-          band_column<MODE, AFFINE, PROF, TB, decltype(checked)::value, R>(tab, prof, in_c, pw, go, ge, goe, nu, hl, f, bv,
-                                                                          bj, hk, j, rn, hd, hup, eup, hn, word);
+          // local affine score-only bands fold the floor into E (band.h)
+          constexpr bool kFloorE = MODE == ALN_LOCAL && AFFINE && !TB;
+          band_column<MODE, AFFINE, PROF, TB, decltype(checked)::value, R, true, kFloorE>(
+              tab, prof, in_c, pw, go, ge, goe, nu, hl, f, bv, bj, hk, j, rn, hd, hup, eup, hn, word);
           if (TB) codes[j - 1] = (uint16_t)word;
           if (MODE == ALN_SEMIGLOBAL && last_band && rn >= 0 && rn < R && hn > brow) {
             brow = hn;
@@ -1094,8 +1096,10 @@ __global__ __launch_bounds__(kWfBlock) void wf_i32_group_kernel(const KParams P,
           int32_t hn = 0;
           uint32_t word = 0;
           const int pw = PROF == kProfLane ? (int)lp[in_c] : 0;
-          band_column<MODE, AFFINE, PROF, TB, decltype(checked)::value, R>(tab, prof, in_c, pw, go, ge, goe, nu, hl, f, bv,
-                                                                          bj, hk, j, rn, hd, hup, eup, hn, word);
+          // local affine score-only bands fold the floor into E (band.h); checkpoints store E, so not there
+          constexpr bool kFloorE = MODE == ALN_LOCAL && AFFINE && !TB && !CKPT;
+          band_column<MODE, AFFINE, PROF, TB, decltype(checked)::value, R, true, kFloorE>(
+              tab, prof, in_c, pw, go, ge, goe, nu, hl, f, bv, bj, hk, j, rn, hd, hup, eup, hn, word);
           if (TB) codes[j - 1] = (uint16_t)word;
           if (MODE == ALN_SEMIGLOBAL && last_band && rn >= 0 && rn < R && hn > brow) {
             brow = hn;
