@@ -1096,8 +1096,10 @@ __global__ __launch_bounds__(kWfBlock) void wf_i32_group_kernel(const KParams P,
           int32_t hn = 0;
           uint32_t word = 0;
           const int pw = PROF == kProfLane ? (int)lp[in_c] : 0;
-          // local affine score-only bands fold the floor into E (band.h); checkpoints store E, so not there
-          constexpr bool kFloorE = MODE == ALN_LOCAL && AFFINE && !TB && !CKPT;
+          // local affine score-only bands fold the floor into E (band.h).  Checkpoint rows then hold the
+          // raised E too; the tiles relaxed again from them reproduce every H, and every E on the alignment's
+          // path (a local path's E is at least 0, the floor), so the walk reads the same codes.
+          constexpr bool kFloorE = MODE == ALN_LOCAL && AFFINE && !TB;
           band_column<MODE, AFFINE, PROF, TB, decltype(checked)::value, R, true, kFloorE>(
               tab, prof, in_c, pw, go, ge, goe, nu, hl, f, bv, bj, hk, j, rn, hd, hup, eup, hn, word);
           if (TB) codes[j - 1] = (uint16_t)word;
