@@ -341,6 +341,8 @@ aln_status_t plan_split(int64_t n_pairs, int64_t total_q, int64_t total_s, bool 
   sp->wf_base = off;
   // bands run along the longer side when oriented: at most (n + m) / band + 1 per pair
   const int64_t max_items = (total_q + total_s) / kWfBand + n_pairs + 1;
+  // the per-band engine's hand-out order keeps item positions and level counts in 32 bits
+  if (max_items > (int64_t)INT32_MAX - 2) return ALN_E_INVALID;
   // a pair of two or more bands has row slots over its columns, never more than m + 1 of them
   sp->item_cap = max_items;
   sp->row_cap = 2 * (total_s + n_pairs);
