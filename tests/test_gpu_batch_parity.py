@@ -421,3 +421,37 @@ def test_local_int16_beyond_the_bound(gpu, tb):
     assert not bad, "\n".join(bad[:10])
     redo = (gres["flags"] & aln.RES_INT32_REDO) != 0
     assert not redo[:-2].any() and redo[-2:].all()
+
+
+@pytest.mark.parametrize("tb", [False, True], ids=["score", "cigar"])
+def test_per_band_level_order(gpu, tb):
+    """The per-band engine hands its bands out level by level (band 0 of every pair, then band 1, ...): a
+    batch of pairs with 1 to 12 bands in shuffled order, some with an empty side, every pair on the band
+    wavefront and the engine forced to one wave per band, is exact against the oracle, score and end cell
+    (and CIGAR).  Pairs of one band, pairs whose bands outnumber the others' and empty pairs share the
+    levels."""
+    import paper_2002_04561_amd as aln
+    rng = np.random.default_rng(4711 + tb)
+    qs, ss = [], []
+    for k in range(160):
+        nb = int(rng.integers(1, 13))
+        n = int(rng.integers((nb - 1) * 256 + 1, nb * 256 + 1))
+        m = int(rng.integers(1, 900)) if k % 9 else 0
+        a = rng.integers(0, 4, n, dtype=np.uint8)
+        if m and rng.random() < 0.6:
+            b = synth.mutate_geometric(rng, a, 0.06, 0.01, 3.0)[:m]
+            if len(b) < m:
+                b = np.concatenate([b, rng.integers(0, 4, m - len(b), dtype=np.uint8)])
+        else:
+            b = rng.integers(0, 4, m, dtype=np.uint8)
+        qs.append(a)
+        ss.append(b)
+    q, qo = synth.pack(qs)
+    s, so = synth.pack(ss)
+    w = synth.Workload("level_order", synth.LOCAL, 4, -3, -1, q, qo, s, so, match=2, mismatch=-3)
+    cfg = aln.BatchConfig(wf_min_cells=1, wf_group=1, wf_orient=0)
+    flags = aln.TRACEBACK if tb else aln.SCORE_ONLY
+    gres, gcig = run_gpu(w, flags, config=cfg)
+    ores, ocig = run_oracle(w, tb)
+    bad = compare(w, gres, gcig, ores, ocig, "level order/%s" % ("cigar" if tb else "score"))
+    assert not bad, "\n".join(bad[:10])
