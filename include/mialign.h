@@ -168,7 +168,7 @@ aln_status_t aln_align_batch(const aln_scoring_t* scoring, int64_t n_pairs, cons
  *   wf_group         wavefront engine: 1 => every band on its own wave, hand-offs through HBM;
  *                    4 => workgroups of 4 consecutive bands handing rows over in LDS, with a courier
  *                    wave for the hand-offs to and from other workgroups.  0 => 4 when the batch has
- *                    fewer than 16 bands per compute unit (estimated from total_q + total_s), else 1.
+ *                    fewer than 56 bands per compute unit (estimated from total_q + total_s), else 1.
  *                    aln_align_long always uses 4.
  *   wf_bits          wavefront engine, grouped bands of score-only local alignments over alphabets
  *                    of up to 32 letters: 16 => packed 16-bit cells (two half bands per lane, scores

@@ -351,9 +351,10 @@ aln_status_t plan_split(int64_t n_pairs, int64_t total_q, int64_t total_s, bool 
   sp->wf_waves = wf_waves(cfg.wf_waves_per_cu);
   // Groups of bands pay off when the batch has few bands per SIMD: then each compute wave is alone
   // on its SIMD and nothing hides its device-memory waits.  Bands are estimated from the letters
-  // (rows along the longer sequence, 256 per band).
+  // (rows along the longer sequence, 256 per band).  On uneven protein batches the per-band engine
+  // (bands handed out level by level) overtakes between 46 and 70 estimated bands per compute unit.
   const int64_t est_bands = (total_q + total_s) / (2 * kWfBand);
-  sp->grouped = cfg.wf_group == 4 || (cfg.wf_group == 0 && est_bands < (int64_t)16 * (cus > 0 ? cus : 1));
+  sp->grouped = cfg.wf_group == 4 || (cfg.wf_group == 0 && est_bands < (int64_t)56 * (cus > 0 ? cus : 1));
   if (sp->grouped && !cfg.waves_given && cus > 0) {
     // Workgroups take their groups in the order they start, wherever they sit, so a grid with more
     // workgroups than groups can stack several working ones on a compute unit while others idle.
