@@ -127,7 +127,7 @@ __device__ __forceinline__ bool better(int s1, int i1, int j1, int s2, int i2, i
   return s1 > s2 || (s1 == s2 && (i1 < i2 || (i1 == i2 && j1 < j2)));
 }
 
-// Bands on their own (one wave per band, hand-offs through HBM).
+// Bands on their own (one wave per band, hand-offs through HBM), handed out level by level (wf_order_kernel).
 //
 // Values are kept with a row bias: Hb(i,j) = H(i,j) - i*ge, and likewise E and F.  Then
 //   Eb(i,j) = max(Eb(i-1,j), Hb(i-1,j) + go)          (extension costs nothing: one add less)
@@ -1375,8 +1375,8 @@ __global__ void wf_reset_kernel(WfWs W) {
 // above it, idle -- a fifth of the waves' time on square pairs, whatever their size -- while other
 // pairs' bands could have run.  Level by level, a band is handed out only after every band of the
 // level above, so band b - 1 of its pair is always already running (no deadlock, whatever the
-// residency) and usually far ahead.  On the uneven protein batch this took the call from 250 to about
-// 177 ms; chunks of 64 to 16384 pairs ordered this way, one chunk after the other, gave 230 to 177.
+// residency) and usually far ahead.  On the uneven protein batch this took the call from 250 to 175 ms;
+// chunks of 64 to 16384 pairs ordered this way, one chunk after the other, gave 230 to 177.
 //
 // W.lv: [0] the largest band count, [1 .. L] the pairs with exactly b bands, then the first position
 // of level b, [L + 1 ..] the level cursors (L = W.n_lv - 1 entries each, cleared by wf_reset_kernel).
